@@ -1,0 +1,218 @@
+/*
+ * fks.h - C ABI of the MI355X (gfx950) fast spectral Boltzmann collision library.
+ *
+ * The library evaluates, independently in every spatial cell, the fast spectral
+ * approximation of the variable-hard-sphere (VHS) Boltzmann collision operator
+ * Q(f,f) of Dimarco, Loubere, Narski and Rey (Section 3.3: eqs. ode, FKM and the
+ * decoupled 3D formula), applies the L2 conservation projection of Section 3.2
+ * (eq. minim1) and the forward-Euler collision update of Section 3.1
+ * (eq. f_coll, with the 1/tau rescaling of Part 2), and performs the exact FKS
+ * transport shift of piecewise-constant data (Section 3.1 eq. f_bar, particle
+ * form of Section 4.1).
+ *
+ * Conventions shared by every entry point
+ *   - Velocity grid: n points per axis on [-T, T), nodes v_j = -T + j*2T/n.
+ *     A cell's distribution is n^3 FP64 values in C order f[x][y][z].
+ *   - Batches are cell-major: f[cell][x][y][z], contiguous.
+ *   - Pointers documented as "device" must be device memory of the current
+ *     HIP device; "host" pointers are ordinary host memory.  The caller owns
+ *     every array; the library never frees caller memory.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *     All device work of a call is enqueued on that stream; calls return
+ *     after enqueueing (asynchronously) unless stated otherwise.
+ *   - Every function returns fks_status; nothing throws across the ABI.
+ *     Argument validation happens before anything is enqueued, so an
+ *     FKS_ERR_INVALID / FKS_ERR_UNSUPPORTED return leaves all buffers untouched.
+ */
+#ifndef FKS_H
+#define FKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FKS_OK = 0,
+    FKS_ERR_INVALID = -1,      /* bad argument, size or pointer */
+    FKS_ERR_UNSUPPORTED = -2,  /* valid request outside the implemented set (e.g. odd n) */
+    FKS_ERR_NOMEM = -3,        /* device allocation failed (plan creation only) */
+    FKS_ERR_DEVICE = -4,       /* a HIP runtime call or kernel launch failed */
+    FKS_ERR_NUMERIC = -5       /* reserved: non-finite data detected */
+} fks_status;
+
+typedef enum {
+    FKS_PREC_F64 = 0,          /* plain FP64 path: transforms, products and fix in FP64 */
+    FKS_PREC_F32_FIX64 = 1     /* FP32 transforms/products, FP64 moments + projection + update */
+} fks_precision;
+
+typedef enum {
+    FKS_RULE_GAUSS = 0,        /* cos(theta_p) Gauss-Legendre, uniform azimuth (default) */
+    FKS_RULE_MIDPOINT = 1      /* theta_p = (p+1/2)pi/n_polar with sin(theta) Jacobian */
+} fks_dir_rule;
+
+/* Path selection flags (fks_plan_desc.flags). */
+#define FKS_FLAG_FORCE_GENERIC 0x1u  /* use the multi-pass path even where the fused kernel exists */
+
+/*
+ * Operator description (Section 3.3).  Zero / non-positive optional fields
+ * take the documented defaults.
+ */
+typedef struct {
+    int32_t n;            /* velocity points per axis; even, 4 <= n <= 48, n = 2^a 3^b */
+    double  T;            /* velocity half-box: grid on [-T, T) (T > 0) */
+    double  R;            /* Carleman truncation radius; <= 0 -> 2T/(3+sqrt 2) */
+    double  gamma;        /* VHS exponent, 0 <= gamma <= 1 (1 = hard spheres) */
+    double  c_gamma;      /* kernel constant C_gamma; <= 0 -> 1/(4 pi) */
+    int32_t n_polar;      /* polar nodes A1 (>= 1) */
+    int32_t n_azim;       /* azimuthal nodes A2 (>= 1); M = A1*A2 directions on the half sphere */
+    int32_t rule;         /* fks_dir_rule */
+    int32_t radial_terms; /* K for gamma != 1; 0 -> smallest K with lambda_K/lambda_0 < radial_tol */
+    double  radial_tol;   /* <= 0 -> 1e-4 */
+    int32_t precision;    /* fks_precision */
+    uint32_t flags;       /* FKS_FLAG_* */
+} fks_plan_desc;
+
+typedef struct fks_plan fks_plan;   /* opaque: immutable after creation, owns device tables */
+
+typedef struct {
+    int32_t n;                 /* as described */
+    int32_t M;                 /* directions n_polar*n_azim */
+    int32_t K;                 /* radial terms actually used */
+    int32_t J;                 /* convolution terms per cell: M*K gain terms + 1 loss term */
+    double  R;                 /* truncation radius actually used */
+    double  c_gamma;           /* kernel constant actually used */
+    int32_t precision;         /* fks_precision */
+    int32_t fused;             /* 1 if fks_collide_batch uses the single fused kernel */
+    size_t  table_bytes;       /* device bytes held by the plan */
+    double  flops_per_cell;    /* algorithmic flop count of one Q evaluation (see design notes) */
+} fks_plan_info;
+
+/*
+ * Creates a plan: directions, radial expansion and the 5x5 Gram matrix of the
+ * collision invariants are computed on the host in FP64; the kernel-mode
+ * tables alpha_{e,r}(k), beta_{e,r}(k) (half spectrum, kz in [0, n/2]) and the
+ * loss table L(k) = B_F(k,k) are computed on the device in FP64, then rounded
+ * to FP32 for the FP32 path.  Blocks until the tables are built.
+ * Errors: FKS_ERR_INVALID (NULL pointers, out-of-range fields),
+ * FKS_ERR_UNSUPPORTED (n odd or not 2^a 3^b, n > 48), FKS_ERR_NOMEM, FKS_ERR_DEVICE.
+ * On error *out is set to NULL.
+ */
+fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan** out);
+
+/* Frees the plan's device memory (synchronises the device first).  NULL is a no-op. */
+fks_status fks_plan_destroy(fks_plan* plan);
+
+/* Fills *info (host).  FKS_ERR_INVALID on NULL. */
+fks_status fks_plan_query(const fks_plan* plan, fks_plan_info* info);
+
+/*
+ * Copies the plan's FP64 tables to host memory, for inspection and tests.
+ * ab_host: [J][n/2+1][n][n][2] doubles = (omega_j * alpha_j(k), beta_j(k)) with
+ * k = (kx, ky, kz) in FFT storage order, kz in [0, n/2]; the last term
+ * (j = J-1) is the loss term (-L(k), 1).  Either pointer may be NULL.
+ * dirs_host: [M][4] doubles = (e_x, e_y, e_z, w_e).  Synchronous.
+ */
+fks_status fks_plan_copy_tables(const fks_plan* plan, double* ab_host, double* dirs_host);
+
+/*
+ * One homogeneous run of cells sharing a plan.
+ *   f      device, const, [ncell][n][n][n] FP64: the post-transport distribution f*.
+ *   q_out  device, [ncell][n^3] FP64, or NULL: receives Q_c, the collision
+ *          operator after the conservation projection (Section 3.2).
+ *   f_out  device, [ncell][n^3] FP64, or NULL: receives f* + dt_over_tau * Q_c
+ *          (eq. f_coll).  May alias f (in-place update); must not overlap q_out.
+ *   At least one of q_out, f_out must be non-NULL.  ncell >= 0 (0 = nothing).
+ */
+typedef struct {
+    const fks_plan* plan;
+    const double*   f;
+    double*         q_out;
+    double*         f_out;
+    int64_t         ncell;
+    double          dt_over_tau;
+} fks_segment;
+
+/* Device workspace bytes needed by fks_collide_batch for these segments (host call). */
+fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes);
+
+/*
+ * Evaluates Q(f,f) for every cell of every segment (fast spectral form with
+ * Nyquist planes zeroed), projects it onto the kernel of the collision
+ * invariants in FP64 and writes q_out / f_out.  workspace: device memory of at
+ * least fks_workspace_size bytes, owned by the caller, not used concurrently
+ * by another call.  No device allocation happens inside.
+ * Errors: FKS_ERR_INVALID (NULL plan/f, both outputs NULL, ncell < 0, small
+ * workspace), FKS_ERR_DEVICE (launch failure).
+ */
+fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace,
+                             size_t ws_bytes, void* hip_stream);
+
+/*
+ * Moments U = C f (eq. i5 on the grid, C of Section 3.2): for each cell
+ * U[cell] = dv^3 * sum_j f_j (1, v_x, v_y, v_z, |v|^2)  (FP64).
+ * f device [ncell][n^3]; U device [ncell][5].  FP64 throughout.
+ */
+fks_status fks_moments(const double* f, int64_t ncell, int32_t n, double T, double* U,
+                       void* hip_stream);
+
+/*
+ * L2 projection of every cell onto prescribed moments (eq. minim1):
+ * f <- f + C^T (C C^T)^{-1} (U_target - C f).  f device [ncell][n^3] in/out;
+ * U_target device [ncell][5] in the units of fks_moments.  FP64.
+ */
+fks_status fks_conserve(double* f, const double* U_target, int64_t ncell, int32_t n, double T,
+                        void* hip_stream);
+
+/* Spatial grid of the transport step: cells f[iz][iy][ix][n^3]. */
+#define FKS_BC_PERIODIC 0
+#define FKS_BC_DIRICHLET 1
+typedef struct {
+    int32_t nx, ny, nz;        /* cells per axis (>= 1) */
+    double  dx;                /* cell width (> 0), equal on every axis */
+    int32_t bc[3];             /* per axis (x, y, z): FKS_BC_PERIODIC or FKS_BC_DIRICHLET */
+} fks_space_desc;
+
+/*
+ * Exact transport of piecewise-constant data (Section 3.1 eq. f_bar) in the
+ * particle form of Section 4.1: per velocity component the accumulated
+ * displacement s is advanced by v dt, and every velocity's mass moves by the
+ * change of d = floor(s/dx + 1/2) cells.
+ *   f_in   device, const [nz][ny][nx][n^3] FP64.
+ *   f_out  device [nz][ny][nx][n^3] FP64; must not overlap f_in.
+ *   offsets host [3][n] FP64, in/out: accumulated displacement of each 1D
+ *          velocity index along x, y, z; updated by this call.
+ *   bc_f   device [6][n^3] FP64 inflow states (faces x-, x+, y-, y+, z-, z+),
+ *          read where a Dirichlet axis pulls mass from outside; may be NULL
+ *          if no axis is Dirichlet.
+ * Any integer shift is handled (periodic wrap or inflow); CFL <= 1 keeps it
+ * within one cell.  Errors: FKS_ERR_INVALID.
+ */
+fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_space_desc* space,
+                               int32_t n, double T, double dt, double* offsets,
+                               const double* bc_f, void* hip_stream);
+
+/* Static string for a status code. */
+const char* fks_status_string(fks_status status);
+
+/*
+ * Host-only helpers (no device needed), exposed so that the host precompute
+ * can be checked without a GPU.
+ *   fks_desc_validate: the validation fks_plan_create performs.
+ *   fks_host_sphere_rule: directions and weights of the half-sphere rule,
+ *     e_w [n_polar*n_azim][4] = (e_x, e_y, e_z, w).
+ *   fks_host_radial_terms: radial expansion for gamma (K requested, 0 -> by tol);
+ *     *K_out receives K; nodes [nq], coef [nq][K] (row-major) may be NULL to query K.
+ */
+fks_status fks_desc_validate(const fks_plan_desc* desc);
+fks_status fks_host_sphere_rule(int32_t n_polar, int32_t n_azim, int32_t rule, double* e_w);
+fks_status fks_host_radial_terms(double gamma, double R, int32_t K, double tol, int32_t nq,
+                                 int32_t* K_out, double* nodes, double* coef);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKS_H */

@@ -1,0 +1,319 @@
+"""Python binding of libfks.so, the MI355X fast spectral Boltzmann collision library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library (C ABI declared in ``include/fks.h``).  Device arrays are torch tensors
+on the current HIP device; calls are enqueued on torch's current stream.
+
+The library is loaded lazily on first use; if ``libfks.so`` has not been built
+the call raises ``RuntimeError`` (there is no fallback implementation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfks.so")
+
+FKS_OK = 0
+FKS_ERR_INVALID = -1
+FKS_ERR_UNSUPPORTED = -2
+FKS_ERR_NOMEM = -3
+FKS_ERR_DEVICE = -4
+FKS_ERR_NUMERIC = -5
+
+PREC_F64 = 0
+PREC_F32_FIX64 = 1
+RULE_GAUSS = 0
+RULE_MIDPOINT = 1
+FLAG_FORCE_GENERIC = 0x1
+BC_PERIODIC = 0
+BC_DIRICHLET = 1
+
+EXPORTED = [
+    "fks_plan_create", "fks_plan_destroy", "fks_plan_query", "fks_plan_copy_tables",
+    "fks_workspace_size", "fks_collide_batch", "fks_moments", "fks_conserve",
+    "fks_transport_shift", "fks_status_string", "fks_desc_validate",
+    "fks_host_sphere_rule", "fks_host_radial_terms",
+]
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("T", C.c_double), ("R", C.c_double), ("gamma", C.c_double),
+        ("c_gamma", C.c_double), ("n_polar", C.c_int32), ("n_azim", C.c_int32),
+        ("rule", C.c_int32), ("radial_terms", C.c_int32), ("radial_tol", C.c_double),
+        ("precision", C.c_int32), ("flags", C.c_uint32),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("M", C.c_int32), ("K", C.c_int32), ("J", C.c_int32),
+        ("R", C.c_double), ("c_gamma", C.c_double), ("precision", C.c_int32),
+        ("fused", C.c_int32), ("table_bytes", C.c_size_t), ("flops_per_cell", C.c_double),
+    ]
+
+
+class Segment(C.Structure):
+    _fields_ = [
+        ("plan", C.c_void_p), ("f", C.c_void_p), ("q_out", C.c_void_p), ("f_out", C.c_void_p),
+        ("ncell", C.c_int64), ("dt_over_tau", C.c_double),
+    ]
+
+
+class SpaceDesc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dx", C.c_double),
+        ("bc", C.c_int32 * 3),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads libfks.so (once).  Raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1608_08009_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    L.fks_plan_create.argtypes = [C.POINTER(PlanDesc), vp, C.POINTER(vp)]
+    L.fks_plan_destroy.argtypes = [vp]
+    L.fks_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
+    L.fks_plan_copy_tables.argtypes = [vp, vp, vp]
+    L.fks_workspace_size.argtypes = [C.POINTER(Segment), i32, C.POINTER(sz)]
+    L.fks_collide_batch.argtypes = [C.POINTER(Segment), i32, vp, sz, vp]
+    L.fks_moments.argtypes = [vp, i64, i32, dbl, vp, vp]
+    L.fks_conserve.argtypes = [vp, vp, i64, i32, dbl, vp]
+    L.fks_transport_shift.argtypes = [vp, vp, C.POINTER(SpaceDesc), i32, dbl, dbl, vp, vp, vp]
+    L.fks_status_string.argtypes = [i32]
+    L.fks_status_string.restype = C.c_char_p
+    L.fks_desc_validate.argtypes = [C.POINTER(PlanDesc)]
+    L.fks_host_sphere_rule.argtypes = [i32, i32, i32, vp]
+    L.fks_host_radial_terms.argtypes = [dbl, dbl, i32, dbl, i32, C.POINTER(i32), vp, vp]
+    for name in EXPORTED:
+        if name != "fks_status_string":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class FksError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {lib().fks_status_string(status).decode()} ({status})")
+
+
+def _check(status: int, what: str) -> None:
+    if status != FKS_OK:
+        raise FksError(status, what)
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _require_device_f64(t, name: str, numel: int | None = None):
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous float64")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+@dataclass
+class Desc:
+    """Operator description, mirrors fks_plan_desc (defaults resolved by the library)."""
+    n: int
+    T: float
+    gamma: float = 1.0
+    R: float = 0.0
+    c_gamma: float = 0.0
+    n_polar: int = 8
+    n_azim: int = 4
+    rule: int = RULE_GAUSS
+    radial_terms: int = 0
+    radial_tol: float = 0.0
+    precision: int = PREC_F32_FIX64
+    flags: int = 0
+
+    def c(self) -> PlanDesc:
+        return PlanDesc(self.n, self.T, self.R, self.gamma, self.c_gamma, self.n_polar, self.n_azim,
+                        self.rule, self.radial_terms, self.radial_tol, self.precision, self.flags)
+
+
+def desc_validate(d: Desc) -> int:
+    cd = d.c()
+    return lib().fks_desc_validate(C.byref(cd))
+
+
+class Plan:
+    """Owns an fks_plan (device tables).  Use as a context manager or call close()."""
+
+    def __init__(self, desc: Desc, stream=None):
+        self.desc = desc
+        h = C.c_void_p()
+        cd = desc.c()
+        _check(lib().fks_plan_create(C.byref(cd), C.c_void_p(_stream_ptr(stream)), C.byref(h)),
+               "fks_plan_create")
+        self._h = h
+        info = PlanInfo()
+        _check(lib().fks_plan_query(h, C.byref(info)), "fks_plan_query")
+        self.info = info
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return self.info.n
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().fks_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tables(self):
+        """(ab [J, n/2+1, n, n, 2] FP64 numpy, dirs [M, 4]) copied from the device."""
+        import numpy as np
+        n, J, M = self.info.n, self.info.J, self.info.M
+        ab = np.empty((J, n // 2 + 1, n, n, 2), dtype=np.float64)
+        dirs = np.empty((M, 4), dtype=np.float64)
+        _check(lib().fks_plan_copy_tables(self.handle, ab.ctypes.data, dirs.ctypes.data),
+               "fks_plan_copy_tables")
+        return ab, dirs
+
+
+def _segments(items):
+    arr = (Segment * len(items))()
+    for i, (plan, f, q_out, f_out, ncell, dt) in enumerate(items):
+        arr[i] = Segment(plan.handle.value if plan is not None else None, _ptr(f), _ptr(q_out),
+                         _ptr(f_out), ncell, dt)
+    return arr
+
+
+def workspace_size(segments) -> int:
+    """segments: list of (plan, f, q_out, f_out, ncell, dt_over_tau)."""
+    arr = _segments(segments)
+    out = C.c_size_t()
+    _check(lib().fks_workspace_size(arr, len(segments), C.byref(out)), "fks_workspace_size")
+    return out.value
+
+
+def collide_batch(segments, workspace=None, stream=None):
+    """fks_collide_batch over segments (plan, f, q_out, f_out, ncell, dt_over_tau).
+
+    ``workspace`` is a uint8 device tensor of at least workspace_size() bytes
+    (the library rejects a smaller one); allocated here if None.  Returns the
+    workspace tensor (reuse it).
+    """
+    import torch
+    for (plan, f, q_out, f_out, ncell, dt) in segments:
+        nn = ncell * plan.n ** 3
+        _require_device_f64(f, "f", nn)
+        _require_device_f64(q_out, "q_out", nn)
+        _require_device_f64(f_out, "f_out", nn)
+    if workspace is None:
+        need = workspace_size(segments)
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    arr = _segments(segments)
+    _check(lib().fks_collide_batch(arr, len(segments), C.c_void_p(_ptr(workspace)), workspace.numel(),
+                                   C.c_void_p(_stream_ptr(stream))), "fks_collide_batch")
+    return workspace
+
+
+def collide(plan: Plan, f, q_out=None, f_out=None, dt_over_tau: float = 0.0, workspace=None, stream=None):
+    """Single-segment convenience wrapper; f is [ncell, n, n, n] float64 on the GPU."""
+    ncell = f.shape[0] if f.dim() == 4 else 1
+    return collide_batch([(plan, f, q_out, f_out, ncell, dt_over_tau)], workspace, stream)
+
+
+def moments(f, n: int, T: float, U=None, stream=None):
+    """U[ncell, 5] = dv^3 sum f (1, v, |v|^2) (FP64, device)."""
+    import torch
+    ncell = f.numel() // n ** 3
+    _require_device_f64(f, "f", ncell * n ** 3)
+    if U is None:
+        U = torch.empty((ncell, 5), dtype=torch.float64, device=f.device)
+    _require_device_f64(U, "U", ncell * 5)
+    _check(lib().fks_moments(C.c_void_p(_ptr(f)), ncell, n, T, C.c_void_p(_ptr(U)),
+                             C.c_void_p(_stream_ptr(stream))), "fks_moments")
+    return U
+
+
+def conserve(f, U, n: int, T: float, stream=None):
+    """In-place projection of every cell of f onto the moments U (eq. minim1)."""
+    ncell = f.numel() // n ** 3
+    _require_device_f64(f, "f", ncell * n ** 3)
+    _require_device_f64(U, "U", ncell * 5)
+    _check(lib().fks_conserve(C.c_void_p(_ptr(f)), C.c_void_p(_ptr(U)), ncell, n, T,
+                              C.c_void_p(_stream_ptr(stream))), "fks_conserve")
+    return f
+
+
+def transport_shift(f_in, f_out, nx: int, ny: int, nz: int, dx: float, bc, n: int, T: float,
+                    dt: float, offsets, bc_f=None, stream=None):
+    """FKS transport step f_in -> f_out; offsets is a host float64 numpy array [3, n] (updated)."""
+    import numpy as np
+    total = nx * ny * nz * n ** 3
+    _require_device_f64(f_in, "f_in", total)
+    _require_device_f64(f_out, "f_out", total)
+    if bc_f is not None:
+        _require_device_f64(bc_f, "bc_f", 6 * n ** 3)
+    if not (isinstance(offsets, np.ndarray) and offsets.dtype == np.float64 and offsets.size == 3 * n
+            and offsets.flags.c_contiguous):
+        raise ValueError("offsets must be a contiguous float64 numpy array of 3*n values")
+    sp = SpaceDesc(nx, ny, nz, dx, (C.c_int32 * 3)(*bc))
+    _check(lib().fks_transport_shift(C.c_void_p(_ptr(f_in)), C.c_void_p(_ptr(f_out)), C.byref(sp), n, T, dt,
+                                     C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(bc_f)),
+                                     C.c_void_p(_stream_ptr(stream))), "fks_transport_shift")
+
+
+def host_sphere_rule(n_polar: int, n_azim: int, rule: int = RULE_GAUSS):
+    import numpy as np
+    out = np.empty((n_polar * n_azim, 4), dtype=np.float64)
+    _check(lib().fks_host_sphere_rule(n_polar, n_azim, rule, out.ctypes.data), "fks_host_sphere_rule")
+    return out
+
+
+def host_radial_terms(gamma: float, R: float, K: int = 0, tol: float = 1e-4, nq: int = 200):
+    import numpy as np
+    k = C.c_int32()
+    _check(lib().fks_host_radial_terms(gamma, R, K, tol, nq, C.byref(k), None, None), "fks_host_radial_terms")
+    nodes = np.empty(nq, dtype=np.float64)
+    coef = np.empty((nq, k.value), dtype=np.float64)
+    _check(lib().fks_host_radial_terms(gamma, R, k.value, tol, nq, C.byref(k), nodes.ctypes.data,
+                                       coef.ctypes.data), "fks_host_radial_terms")
+    return k.value, nodes, coef

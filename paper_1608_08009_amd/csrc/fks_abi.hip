@@ -1,0 +1,507 @@
+// C ABI, argument validation and host-side FP64 precompute of the plan.
+//
+// Host precompute (Section 3.3): half-sphere directions and weights, the
+// separable radial expansion of the VHS Carleman kernel, and the Gram matrix
+// of the collision invariants (Section 3.2).  The kernel-mode tables
+// themselves are built on the device (fks_tables.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fks_internal.hpp"
+
+namespace fks {
+
+namespace {
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+bool is_finite(double x) { return std::isfinite(x); }
+}  // namespace
+
+bool supported_n(int n) {
+    if (n < 4 || n > 48 || (n % 2) != 0) return false;
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1;
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n (long double).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        long double z = cosl(pi * (i + 0.75L) / (n + 0.5L));
+        long double pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1; }
+            pp = n * (z * p1 - p0) / (z * z - 1);   // P_n'(z)
+            long double dz = p1 / pp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        {   // derivative at the converged node
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1; }
+            pp = n * (z * p1 - p0) / (z * z - 1);
+        }
+        long double wi = 2 / ((1 - z * z) * pp * pp);
+        x[i] = (double)(-z);          // ascending order
+        x[n - 1 - i] = (double)z;
+        w[i] = w[n - 1 - i] = (double)wi;
+    }
+}
+
+namespace {
+
+// Cyclic Jacobi eigen-decomposition of a symmetric matrix a[n][n] (destroyed).
+// Returns eigenvalues in lam and eigenvectors as columns of v[n][n].
+void jacobi_eigen(int n, std::vector<double>& a, std::vector<double>& lam, std::vector<double>& v) {
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int p = 0; p < n; ++p) {
+            diag += a[(size_t)p * n + p] * a[(size_t)p * n + p];
+            for (int q = p + 1; q < n; ++q) off += a[(size_t)p * n + q] * a[(size_t)p * n + q];
+        }
+        if (off <= 1e-32 * diag) break;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                double apq = a[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = c * akp - s * akq;
+                    a[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = c * apk - s * aqk;
+                    a[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+                    v[(size_t)k * n + p] = c * vkp - s * vkq;
+                    v[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) lam[i] = a[(size_t)i * n + i];
+}
+
+}  // namespace
+
+// Separable expansion of k(rho, rho') = (rho^2 + rho'^2)^((gamma-1)/2) on [0,R]^2
+// with the measure rho rho' d rho d rho' (Section 3.3, decoupling assumption
+// eq. decoup, extended to K terms): nq graded Gauss-Legendre nodes rho = R u^2,
+// symmetric matrix sqrt(w_i rho_i) k_ij sqrt(w_j rho_j), K leading eigenpairs.
+// coef[i][r] = sqrt(w_i rho_i) U_ir sqrt(lambda_r).  Returns K.
+int radial_expansion(double gamma, double R, int K, double tol, int nq, std::vector<double>& nodes,
+                     std::vector<double>& coef) {
+    std::vector<double> u, wu;
+    gauss_legendre(nq, u, wu);
+    nodes.assign(nq, 0.0);
+    std::vector<double> sq(nq);
+    for (int i = 0; i < nq; ++i) {
+        double ui = 0.5 * (u[i] + 1.0), wi = 0.5 * wu[i];
+        nodes[i] = R * ui * ui;
+        double w = wi * 2.0 * R * ui;
+        sq[i] = std::sqrt(w * nodes[i]);
+    }
+    std::vector<double> a((size_t)nq * nq);
+    for (int i = 0; i < nq; ++i)
+        for (int j = 0; j < nq; ++j) {
+            double r2 = nodes[i] * nodes[i] + nodes[j] * nodes[j];
+            a[(size_t)i * nq + j] = sq[i] * std::pow(r2, 0.5 * (gamma - 1.0)) * sq[j];
+        }
+    std::vector<double> lam, v;
+    jacobi_eigen(nq, a, lam, v);
+    std::vector<int> order(nq);
+    for (int i = 0; i < nq; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int p, int q) { return lam[p] > lam[q]; });
+    if (K <= 0) {
+        K = nq;
+        for (int r = 0; r < nq; ++r)
+            if (lam[order[r]] / lam[order[0]] < tol) { K = r; break; }
+        K = std::max(K, 1);
+    }
+    K = std::min(K, nq);
+    coef.assign((size_t)nq * K, 0.0);
+    for (int r = 0; r < K; ++r) {
+        int c = order[r];
+        double sl = std::sqrt(std::max(lam[c], 0.0));
+        for (int i = 0; i < nq; ++i) coef[(size_t)i * K + r] = sq[i] * v[(size_t)i * nq + c] * sl;
+    }
+    return K;
+}
+
+// Half-sphere rule: theta over [0, pi] (Gauss-Legendre in cos theta or midpoint
+// with the sin theta Jacobian), azimuth phi_q = q pi / n_azim.  p-major order.
+static void sphere_rule(int n_polar, int n_azim, int rule, std::vector<double>& out) {
+    std::vector<double> ct(n_polar), st(n_polar), wt(n_polar);
+    if (rule == FKS_RULE_GAUSS) {
+        std::vector<double> x, w;
+        gauss_legendre(n_polar, x, w);
+        for (int p = 0; p < n_polar; ++p) {
+            ct[p] = x[p];
+            st[p] = std::sqrt(std::max(0.0, 1.0 - x[p] * x[p]));
+            wt[p] = w[p];
+        }
+    } else {
+        for (int p = 0; p < n_polar; ++p) {
+            double th = (p + 0.5) * kPi / n_polar;
+            ct[p] = std::cos(th);
+            st[p] = std::sin(th);
+            wt[p] = st[p] * kPi / n_polar;
+        }
+    }
+    out.assign((size_t)n_polar * n_azim * 4, 0.0);
+    for (int p = 0; p < n_polar; ++p)
+        for (int q = 0; q < n_azim; ++q) {
+            double ph = q * kPi / n_azim;
+            double* o = &out[((size_t)p * n_azim + q) * 4];
+            o[0] = st[p] * std::cos(ph);
+            o[1] = st[p] * std::sin(ph);
+            o[2] = ct[p];
+            o[3] = wt[p] * kPi / n_azim;
+        }
+}
+
+// Gram matrix of the scaled invariants over the grid, inverted in long double.
+GridConst grid_const(int n, double T) {
+    GridConst g{};
+    g.T = T;
+    g.dv = 2.0 * T / n;
+    long double G[5][5] = {};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                long double vx = (-T + i * g.dv) / T, vy = (-T + j * g.dv) / T, vz = (-T + k * g.dv) / T;
+                long double ph[5] = {1.0L, vx, vy, vz, vx * vx + vy * vy + vz * vz};
+                for (int a = 0; a < 5; ++a)
+                    for (int b = 0; b < 5; ++b) G[a][b] += ph[a] * ph[b];
+            }
+    long double A[5][10] = {};
+    for (int a = 0; a < 5; ++a) {
+        for (int b = 0; b < 5; ++b) A[a][b] = G[a][b];
+        A[a][5 + a] = 1.0L;
+    }
+    for (int c = 0; c < 5; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 5; ++r)
+            if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+        for (int k = 0; k < 10; ++k) std::swap(A[c][k], A[piv][k]);
+        long double d = A[c][c];
+        for (int k = 0; k < 10; ++k) A[c][k] /= d;
+        for (int r = 0; r < 5; ++r)
+            if (r != c) {
+                long double m = A[r][c];
+                for (int k = 0; k < 10; ++k) A[r][k] -= m * A[c][k];
+            }
+    }
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) g.ginv[a * 5 + b] = (double)A[a][5 + b];
+    return g;
+}
+
+// Resolves defaults and checks ranges; used by fks_desc_validate and plan creation.
+static fks_status resolve_desc(const fks_plan_desc* in, fks_plan_desc* out) {
+    if (!in) return FKS_ERR_INVALID;
+    fks_plan_desc d = *in;
+    if (!is_finite(d.T) || d.T <= 0) return FKS_ERR_INVALID;
+    if (!is_finite(d.gamma) || d.gamma < 0.0 || d.gamma > 1.0) return FKS_ERR_INVALID;
+    if (!is_finite(d.R) || !is_finite(d.c_gamma) || !is_finite(d.radial_tol)) return FKS_ERR_INVALID;
+    if (d.n_polar < 1 || d.n_azim < 1 || d.n_polar > 256 || d.n_azim > 256) return FKS_ERR_INVALID;
+    if (d.rule != FKS_RULE_GAUSS && d.rule != FKS_RULE_MIDPOINT) return FKS_ERR_INVALID;
+    if (d.precision != FKS_PREC_F64 && d.precision != FKS_PREC_F32_FIX64) return FKS_ERR_INVALID;
+    if (d.radial_terms < 0 || d.radial_terms > 200) return FKS_ERR_INVALID;
+    if ((d.flags & ~FKS_FLAG_FORCE_GENERIC) != 0) return FKS_ERR_INVALID;
+    if (d.n <= 0) return FKS_ERR_INVALID;
+    if (!supported_n(d.n)) return FKS_ERR_UNSUPPORTED;
+    if (d.R <= 0) d.R = 2.0 * d.T / (3.0 + std::sqrt(2.0));
+    if (d.c_gamma <= 0) d.c_gamma = 1.0 / (4.0 * kPi);
+    if (d.radial_tol <= 0) d.radial_tol = 1e-4;
+    if (out) *out = d;
+    return FKS_OK;
+}
+
+}  // namespace fks
+
+using namespace fks;
+
+extern "C" {
+
+const char* fks_status_string(fks_status s) {
+    switch (s) {
+        case FKS_OK: return "FKS_OK";
+        case FKS_ERR_INVALID: return "FKS_ERR_INVALID: invalid argument";
+        case FKS_ERR_UNSUPPORTED: return "FKS_ERR_UNSUPPORTED: request outside the implemented set";
+        case FKS_ERR_NOMEM: return "FKS_ERR_NOMEM: device allocation failed";
+        case FKS_ERR_DEVICE: return "FKS_ERR_DEVICE: HIP runtime or launch failure";
+        case FKS_ERR_NUMERIC: return "FKS_ERR_NUMERIC: non-finite data";
+    }
+    return "unknown fks_status";
+}
+
+fks_status fks_desc_validate(const fks_plan_desc* desc) { return resolve_desc(desc, nullptr); }
+
+fks_status fks_host_sphere_rule(int32_t n_polar, int32_t n_azim, int32_t rule, double* e_w) {
+    if (!e_w || n_polar < 1 || n_azim < 1 || n_polar > 256 || n_azim > 256) return FKS_ERR_INVALID;
+    if (rule != FKS_RULE_GAUSS && rule != FKS_RULE_MIDPOINT) return FKS_ERR_INVALID;
+    std::vector<double> out;
+    sphere_rule(n_polar, n_azim, rule, out);
+    std::memcpy(e_w, out.data(), out.size() * sizeof(double));
+    return FKS_OK;
+}
+
+fks_status fks_host_radial_terms(double gamma, double R, int32_t K, double tol, int32_t nq,
+                                 int32_t* K_out, double* nodes, double* coef) {
+    if (!K_out || !(gamma >= 0.0 && gamma <= 1.0) || !(R > 0) || K < 0 || nq < 2 || nq > 2000)
+        return FKS_ERR_INVALID;
+    std::vector<double> nd, cf;
+    int k = radial_expansion(gamma, R, K, tol > 0 ? tol : 1e-4, nq, nd, cf);
+    *K_out = k;
+    if (nodes) std::memcpy(nodes, nd.data(), nd.size() * sizeof(double));
+    if (coef) std::memcpy(coef, cf.data(), cf.size() * sizeof(double));
+    return FKS_OK;
+}
+
+fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan** out) {
+    if (!out) return FKS_ERR_INVALID;
+    *out = nullptr;
+    fks_plan_desc d{};
+    fks_status st = resolve_desc(desc, &d);
+    if (st != FKS_OK) return st;
+    fks_plan* p = new (std::nothrow) fks_plan();
+    if (!p) return FKS_ERR_NOMEM;
+    p->desc = d;
+    const int n = d.n;
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FKS_ERR_DEVICE; }
+    p->M = d.n_polar * d.n_azim;
+    if (d.gamma == 1.0) {
+        p->K = 1;   // constant Carleman kernel: closed-form phi, psi
+    } else {
+        p->K = radial_expansion(d.gamma, d.R, d.radial_terms, d.radial_tol, 200, p->rad_nodes, p->rad_coef);
+    }
+    p->J = p->M * p->K + 1;
+    p->H = (n / 2 + 1) * n * n;
+    p->kappa = kPi / d.T;
+    p->gc = grid_const(n, d.T);
+    sphere_rule(d.n_polar, d.n_azim, d.rule, p->dirs);
+    // algorithmic flops: (2 J' + 2) real FFTs of n^3 points at 2.5 n log2 n,
+    // J' = M K packed complex inverse transforms (two real ones each) plus the
+    // forward and loss transforms; 7 flops per point and term for the products
+    // and accumulation; 3 per point for the update.
+    double nn = (double)n * n * n;
+    p->flops_per_cell = (2.0 * p->M * p->K + 2.0) * 2.5 * nn * std::log2(nn) + 7.0 * p->M * p->K * nn + 3.0 * nn;
+    size_t tab_elems = (size_t)p->J * p->H * 2;
+    if (hipMalloc(&p->d_tab64, tab_elems * sizeof(double)) != hipSuccess) {
+        delete p;
+        return FKS_ERR_NOMEM;
+    }
+    p->table_bytes = tab_elems * sizeof(double);
+    if (hipMalloc(&p->d_gc, sizeof(GridConst)) != hipSuccess ||
+        hipMemcpy(p->d_gc, &p->gc, sizeof(GridConst), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->d_tab64);
+        if (p->d_gc) (void)hipFree(p->d_gc);
+        delete p;
+        return FKS_ERR_NOMEM;
+    }
+    if (d.precision == FKS_PREC_F32_FIX64) {
+        if (hipMalloc(&p->d_tab32, tab_elems * sizeof(float)) != hipSuccess) {
+            (void)hipFree(p->d_tab64);
+            (void)hipFree(p->d_gc);
+            delete p;
+            return FKS_ERR_NOMEM;
+        }
+        p->table_bytes += tab_elems * sizeof(float);
+        p->fused = fused_available(n) && !(d.flags & FKS_FLAG_FORCE_GENERIC);
+        if (p->fused) p->fused_grid = fused_grid_size(n, p->device);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (build_tables(p, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipFree(p->d_tab64);
+        (void)hipFree(p->d_gc);
+        if (p->d_tab32) (void)hipFree(p->d_tab32);
+        delete p;
+        return FKS_ERR_DEVICE;
+    }
+    *out = p;
+    return FKS_OK;
+}
+
+fks_status fks_plan_destroy(fks_plan* p) {
+    if (!p) return FKS_OK;
+    fks_status st = FKS_OK;
+    if (hipDeviceSynchronize() != hipSuccess) st = FKS_ERR_DEVICE;
+    if (p->d_tab64) (void)hipFree(p->d_tab64);
+    if (p->d_tab32) (void)hipFree(p->d_tab32);
+    if (p->d_gc) (void)hipFree(p->d_gc);
+    delete p;
+    return st;
+}
+
+fks_status fks_plan_query(const fks_plan* p, fks_plan_info* info) {
+    if (!p || !info) return FKS_ERR_INVALID;
+    info->n = p->desc.n;
+    info->M = p->M;
+    info->K = p->K;
+    info->J = p->J;
+    info->R = p->desc.R;
+    info->c_gamma = p->desc.c_gamma;
+    info->precision = p->desc.precision;
+    info->fused = p->fused ? 1 : 0;
+    info->table_bytes = p->table_bytes;
+    info->flops_per_cell = p->flops_per_cell;
+    return FKS_OK;
+}
+
+fks_status fks_plan_copy_tables(const fks_plan* p, double* ab_host, double* dirs_host) {
+    if (!p) return FKS_ERR_INVALID;
+    if (ab_host) {
+        size_t bytes = (size_t)p->J * p->H * 2 * sizeof(double);
+        if (hipMemcpy(ab_host, p->d_tab64, bytes, hipMemcpyDeviceToHost) != hipSuccess) return FKS_ERR_DEVICE;
+    }
+    if (dirs_host) std::memcpy(dirs_host, p->dirs.data(), p->dirs.size() * sizeof(double));
+    return FKS_OK;
+}
+
+static fks_status check_segment(const fks_segment& s) {
+    if (!s.plan) return FKS_ERR_INVALID;
+    if (s.ncell < 0) return FKS_ERR_INVALID;
+    if (s.ncell == 0) return FKS_OK;
+    if (!s.f || (!s.q_out && !s.f_out)) return FKS_ERR_INVALID;
+    if (!std::isfinite(s.dt_over_tau)) return FKS_ERR_INVALID;
+    size_t bytes = (size_t)s.ncell * s.plan->desc.n * s.plan->desc.n * s.plan->desc.n * sizeof(double);
+    if (s.q_out && s.f_out) {
+        const char* a = (const char*)s.q_out;
+        const char* b = (const char*)s.f_out;
+        if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+    }
+    if (s.q_out) {
+        const char* a = (const char*)s.q_out;
+        const char* b = (const char*)s.f;
+        if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+    }
+    if (s.f_out && s.f_out != s.f) {
+        const char* a = (const char*)s.f_out;
+        const char* b = (const char*)s.f;
+        if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+    }
+    return FKS_OK;
+}
+
+static size_t segment_ws(const fks_segment& s) {
+    if (s.ncell == 0) return 0;
+    return s.plan->fused ? fused_workspace_bytes(s.plan, s.ncell) : generic_workspace_bytes(s.plan, s.ncell);
+}
+
+fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes) {
+    if (!bytes || nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
+    size_t mx = 0;
+    for (int i = 0; i < nseg; ++i) {
+        fks_status st = check_segment(segs[i]);
+        if (st != FKS_OK) return st;
+        mx = std::max(mx, segment_ws(segs[i]));
+    }
+    *bytes = mx;
+    return FKS_OK;
+}
+
+fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
+                             void* hip_stream) {
+    if (nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
+    size_t need = 0;
+    for (int i = 0; i < nseg; ++i) {
+        fks_status st = check_segment(segs[i]);
+        if (st != FKS_OK) return st;
+        need = std::max(need, segment_ws(segs[i]));
+    }
+    if (need > 0 && (!workspace || ws_bytes < need)) return FKS_ERR_INVALID;
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int i = 0; i < nseg; ++i) {
+        const fks_segment& g = segs[i];
+        if (g.ncell == 0) continue;
+        hipError_t e = g.plan->fused ? collide_fused(g.plan, g, workspace, ws_bytes, s)
+                                     : collide_generic(g.plan, g, workspace, ws_bytes, s);
+        if (e != hipSuccess) return FKS_ERR_DEVICE;
+    }
+    return FKS_OK;
+}
+
+fks_status fks_moments(const double* f, int64_t ncell, int32_t n, double T, double* U, void* hip_stream) {
+    if (ncell < 0 || !(T > 0) || !std::isfinite(T) || n < 2 || n > 64) return FKS_ERR_INVALID;
+    if (ncell == 0) return FKS_OK;
+    if (!f || !U) return FKS_ERR_INVALID;
+    return moments(f, ncell, n, T, U, (hipStream_t)hip_stream) == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
+}
+
+fks_status fks_conserve(double* f, const double* U, int64_t ncell, int32_t n, double T, void* hip_stream) {
+    if (ncell < 0 || !(T > 0) || !std::isfinite(T) || n < 2 || n > 64) return FKS_ERR_INVALID;
+    if (ncell == 0) return FKS_OK;
+    if (!f || !U) return FKS_ERR_INVALID;
+    return conserve(f, U, ncell, n, T, (hipStream_t)hip_stream) == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
+}
+
+fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_space_desc* sp, int32_t n,
+                               double T, double dt, double* offsets, const double* bc_f, void* hip_stream) {
+    if (!f_in || !f_out || !sp || !offsets) return FKS_ERR_INVALID;
+    if (n < 2 || n > 64 || !(T > 0) || !std::isfinite(T) || !std::isfinite(dt)) return FKS_ERR_INVALID;
+    if (sp->nx < 1 || sp->ny < 1 || sp->nz < 1 || !(sp->dx > 0) || !std::isfinite(sp->dx)) return FKS_ERR_INVALID;
+    bool any_dirichlet = false;
+    for (int a = 0; a < 3; ++a) {
+        if (sp->bc[a] != FKS_BC_PERIODIC && sp->bc[a] != FKS_BC_DIRICHLET) return FKS_ERR_INVALID;
+        any_dirichlet |= sp->bc[a] == FKS_BC_DIRICHLET;
+    }
+    if (any_dirichlet && !bc_f) return FKS_ERR_INVALID;
+    size_t bytes = (size_t)sp->nx * sp->ny * sp->nz * n * n * n * sizeof(double);
+    const char* a = (const char*)f_in;
+    const char* b = (const char*)f_out;
+    if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+    // per-axis displacement update and integer shifts (host, FP64)
+    ShiftTable sh{};
+    const double dv = 2.0 * T / n;
+    double next[3][64];
+    for (int ax = 0; ax < 3; ++ax)
+        for (int k = 0; k < n; ++k) {
+            double v = -T + k * dv;
+            double s0 = offsets[ax * n + k];
+            double s1 = s0 + v * dt;
+            if (!std::isfinite(s1)) return FKS_ERR_INVALID;
+            double d0 = std::floor(s0 / sp->dx + 0.5), d1 = std::floor(s1 / sp->dx + 0.5);
+            double dd = d1 - d0;
+            if (dd > 127 || dd < -127) return FKS_ERR_INVALID;
+            sh.s[ax][k] = (int8_t)dd;
+            next[ax][k] = s1;
+        }
+    hipError_t e = transport(f_in, f_out, *sp, n, sh, bc_f, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return FKS_ERR_DEVICE;
+    for (int ax = 0; ax < 3; ++ax)
+        for (int k = 0; k < n; ++k) offsets[ax * n + k] = next[ax][k];
+    return FKS_OK;
+}
+
+}  // extern "C"

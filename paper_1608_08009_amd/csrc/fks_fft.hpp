@@ -1,0 +1,194 @@
+// Register-resident small FFTs for the collision kernels (host + device).
+//
+// A length-N transform lives in an array of N complex values; every index is a
+// compile-time constant after template expansion, so the arrays map to
+// registers and all permutations are free.  The recursion is a mixed-radix
+// (4, 2, 3) decimation in time; twiddle factors are exact compile-time
+// constants computed in double precision (then rounded to the working type),
+// and multiplications by 1, -1 and +-i are removed at compile time.
+//
+//   fft<T, N, SIGN>(x):  x[k] <- sum_n x[n] exp(SIGN * 2 pi i n k / N)   (unnormalised)
+#pragma once
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#if defined(__HIPCC__)
+#define FKS_HD __host__ __device__ __forceinline__
+#else
+#define FKS_HD inline
+#endif
+
+namespace fks {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+FKS_HD cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+FKS_HD cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// a * (s i), s = +-1
+template <typename T, int S>
+FKS_HD cx<T> cmul_i(cx<T> a) {
+    if constexpr (S > 0) return {-a.y, a.x};
+    else return {a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// compile-time trigonometry (double): sin/cos(2 pi num/den) by exact octant
+// reduction and Taylor series on [0, pi/4] (within a few ulp of double)
+// ---------------------------------------------------------------------------
+namespace ct {
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double sin_red(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int k = 1; k <= 12; ++k) {
+        term *= -x2 / double((2 * k) * (2 * k + 1));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double cos_red(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k <= 12; ++k) {
+        term *= -x2 / double((2 * k - 1) * (2 * k));
+        sum += term;
+    }
+    return sum;
+}
+// sin and cos of 2 pi num / den
+struct sc { double s, c; };
+constexpr sc sincos2pi(long num, long den) {
+    num %= den;
+    if (num < 0) num += den;
+    // angle = (pi/4) * (8 num / den): octant o, fraction r/den of an octant
+    long e8 = 8 * num;
+    long o = e8 / den;
+    long r = e8 - o * den;              // in [0, den)
+    double a = (kPi / 4.0) * double(r) / double(den);           // in [0, pi/4)
+    double b = (kPi / 4.0) * double(den - r) / double(den);     // pi/4 - a, exact complement
+    double s = 0, c = 0;
+    switch (o) {
+        case 0: s = sin_red(a);  c = cos_red(a);  break;
+        case 1: s = cos_red(b);  c = sin_red(b);  break;
+        case 2: s = cos_red(a);  c = -sin_red(a); break;
+        case 3: s = sin_red(b);  c = -cos_red(b); break;
+        case 4: s = -sin_red(a); c = -cos_red(a); break;
+        case 5: s = -cos_red(b); c = -sin_red(b); break;
+        case 6: s = -cos_red(a); c = sin_red(a);  break;
+        default: s = -sin_red(b); c = cos_red(b); break;
+    }
+    return {s, c};
+}
+}  // namespace ct
+
+// compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1
+template <typename F, int... Is>
+FKS_HD void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+FKS_HD void sfor(F&& f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// multiply by W = exp(SIGN * 2 pi i E / N)
+template <typename T, int SIGN, int N, int E>
+FKS_HD cx<T> twiddle(cx<T> a) {
+    constexpr int e = ((E % N) + N) % N;
+    if constexpr (e == 0) {
+        return a;
+    } else if constexpr (2 * e == N) {
+        return {-a.x, -a.y};
+    } else if constexpr (4 * e == N) {
+        return cmul_i<T, SIGN>(a);
+    } else if constexpr (4 * e == 3 * N) {
+        return cmul_i<T, -SIGN>(a);
+    } else {
+        constexpr ct::sc w = ct::sincos2pi(e, N);
+        constexpr T c = T(w.c);
+        constexpr T s = T(SIGN > 0 ? w.s : -w.s);
+        return {a.x * c - a.y * s, a.x * s + a.y * c};
+    }
+}
+
+template <int N>
+constexpr int first_radix() {
+    return (N % 4 == 0) ? 4 : (N % 2 == 0 ? 2 : (N % 3 == 0 ? 3 : N));
+}
+
+// radix-R butterfly in place: u[q] <- sum_r u[r] exp(SIGN 2 pi i r q / R)
+template <typename T, int R, int SIGN>
+FKS_HD void butterfly(cx<T>* u) {
+    if constexpr (R == 2) {
+        cx<T> a = u[0], b = u[1];
+        u[0] = cadd(a, b);
+        u[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        cx<T> a = cadd(u[0], u[2]);
+        cx<T> b = csub(u[0], u[2]);
+        cx<T> c = cadd(u[1], u[3]);
+        cx<T> d = cmul_i<T, SIGN>(csub(u[1], u[3]));
+        u[0] = cadd(a, c);
+        u[2] = csub(a, c);
+        u[1] = cadd(b, d);
+        u[3] = csub(b, d);
+    } else if constexpr (R == 3) {
+        constexpr T h = T(0.8660254037844386467637231707529362);  // sqrt(3)/2
+        cx<T> s = cadd(u[1], u[2]);
+        cx<T> d = csub(u[1], u[2]);
+        cx<T> m = {u[0].x - T(0.5) * s.x, u[0].y - T(0.5) * s.y};
+        cx<T> t = cmul_i<T, SIGN>(cx<T>{h * d.x, h * d.y});
+        u[0] = cadd(u[0], s);
+        u[1] = cadd(m, t);
+        u[2] = csub(m, t);
+    } else {
+        static_assert(R == 2 || R == 3 || R == 4, "unsupported radix");
+    }
+}
+
+// y[k] = sum_{m<N} x[OFF + IS*m] exp(SIGN 2 pi i m k / N), k = 0..N-1
+template <typename T, int N, int SIGN, int IS, int OFF, int LEN>
+FKS_HD void fft_rec(const cx<T> (&x)[LEN], cx<T>* y) {
+    if constexpr (N == 1) {
+        y[0] = x[OFF];
+    } else {
+        constexpr int R = first_radix<N>();
+        constexpr int M = N / R;
+        cx<T> sub[R][M];
+        sfor<R>([&](auto rI) {
+            constexpr int r = decltype(rI)::value;
+            fft_rec<T, M, SIGN, IS * R, OFF + IS * r, LEN>(x, sub[r]);
+        });
+        sfor<M>([&](auto kI) {
+            constexpr int k = decltype(kI)::value;
+            cx<T> u[R];
+            sfor<R>([&](auto rI) {
+                constexpr int r = decltype(rI)::value;
+                u[r] = twiddle<T, SIGN, N, r * k>(sub[r][k]);
+            });
+            butterfly<T, R, SIGN>(u);
+            sfor<R>([&](auto qI) {
+                constexpr int q = decltype(qI)::value;
+                y[k + M * q] = u[q];
+            });
+        });
+    }
+}
+
+template <typename T, int N, int SIGN>
+FKS_HD void fft(cx<T> (&x)[N]) {
+    cx<T> y[N];
+    fft_rec<T, N, SIGN, 1, 0, N>(x, y);
+    sfor<N>([&](auto kI) {
+        constexpr int k = decltype(kI)::value;
+        x[k] = y[k];
+    });
+}
+
+}  // namespace fks

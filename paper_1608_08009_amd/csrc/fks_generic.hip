@@ -1,0 +1,251 @@
+// Multi-pass collision path (FP64 "plain" path, and FP32 for sizes without a
+// fused kernel).  Every 3D transform is three pencil passes through a device
+// workspace; the conservation projection and update run in FP64.
+//
+// Per chunk of cells:
+//   forward:  x-pass, y-pass, z-pass -> fhat (half spectrum kz in [0, n/2],
+//             scaled by n^-3, Nyquist planes zeroed)                 (eq. FC)
+//   per term j (M*K gain terms, then the loss term):
+//             z-pass with Z = (a_j + i b_j) fhat on input, y-pass,
+//             x-pass with acc += Re(z) Im(z) on output               (eq. ode, fast form)
+//   finish:   FP64 moments of acc, lambda = G^{-1} C acc, Q_c = acc - C^T lambda,
+//             outputs q_out = Q_c and/or f_out = f + dt/tau Q_c      (eqs. minim1, f_coll)
+#include <hip/hip_runtime.h>
+
+#include "fks_common.hpp"
+
+namespace fks {
+namespace {
+
+constexpr int kChunk = 512;   // cells per pass batch
+
+template <typename T>
+struct Tab;
+template <>
+struct Tab<double> {
+    static const cx<double>* get(const fks_plan* p) { return reinterpret_cast<const cx<double>*>(p->d_tab64); }
+};
+template <>
+struct Tab<float> {
+    static const cx<float>* get(const fks_plan* p) { return reinterpret_cast<const cx<float>*>(p->d_tab32); }
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(128) void g_fwd_x(const double* __restrict__ f, cx<T>* __restrict__ work, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int z = t % N, y = (t / N) % N, c = t / (N * N);
+    const double* src = f + (size_t)c * N * N * N + y * N + z;
+    cx<T> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int x = decltype(I)::value;
+        v[x] = cx<T>{T(src[x * N * N]), T(0)};
+    });
+    fft<T, N, -1>(v);
+    cx<T>* dst = work + (size_t)c * N * N * N + y * N + z;
+    sfor<N>([&](auto I) {
+        constexpr int k = decltype(I)::value;
+        dst[k * N * N] = v[k];
+    });
+}
+
+// in-place transform along y for pencils (c, kx, z); SIGN -1 forward, +1 inverse
+template <typename T, int N, int SIGN>
+__global__ __launch_bounds__(128) void g_pass_y(cx<T>* __restrict__ work, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int z = t % N, kx = (t / N) % N, c = t / (N * N);
+    cx<T>* p = work + (size_t)c * N * N * N + kx * N * N + z;
+    cx<T> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int y = decltype(I)::value;
+        v[y] = p[y * N];
+    });
+    fft<T, N, SIGN>(v);
+    sfor<N>([&](auto I) {
+        constexpr int y = decltype(I)::value;
+        p[y * N] = v[y];
+    });
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(128) void g_fwd_z(const cx<T>* __restrict__ work, cx<T>* __restrict__ fh, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
+    const cx<T>* p = work + (size_t)c * N * N * N + (kx * N + ky) * N;
+    cx<T> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int z = decltype(I)::value;
+        v[z] = p[z];
+    });
+    fft<T, N, -1>(v);
+    const T s = T(1.0 / ((double)N * N * N));
+    const bool nyq = (kx == N / 2) || (ky == N / 2);
+    constexpr int H = (N / 2 + 1) * N * N;
+    cx<T>* o = fh + (size_t)c * H + kx * N + ky;
+    sfor<N / 2 + 1>([&](auto I) {
+        constexpr int kz = decltype(I)::value;
+        cx<T> r = (nyq || kz == N / 2) ? cx<T>{T(0), T(0)} : cx<T>{v[kz].x * s, v[kz].y * s};
+        o[kz * N * N] = r;
+    });
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(128) void g_inv_z(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ tab,
+                                               cx<T>* __restrict__ work, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
+    const int mx = (N - kx) % N, my = (N - ky) % N;
+    constexpr int H = (N / 2 + 1) * N * N;
+    const cx<T>* g = fh + (size_t)c * H;
+    cx<T> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int kz = decltype(I)::value;
+        cx<T> a, b;
+        if constexpr (kz <= N / 2) {
+            const int h = (kz * N + kx) * N + ky;
+            a = tab[h];
+            b = g[h];
+        } else {
+            const int h = ((N - kz) * N + mx) * N + my;   // fhat(-k) = conj fhat(k); tables even in k
+            a = tab[h];
+            b = g[h];
+            b.y = -b.y;
+        }
+        v[kz] = cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    });
+    fft<T, N, 1>(v);
+    cx<T>* o = work + (size_t)c * N * N * N + (kx * N + ky) * N;
+    sfor<N>([&](auto I) {
+        constexpr int z = decltype(I)::value;
+        o[z] = v[z];
+    });
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work, T* __restrict__ acc, int C,
+                                               int first) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int z = t % N, y = (t / N) % N, c = t / (N * N);
+    const cx<T>* p = work + (size_t)c * N * N * N + y * N + z;
+    cx<T> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int k = decltype(I)::value;
+        v[k] = p[k * N * N];
+    });
+    fft<T, N, 1>(v);
+    T* q = acc + (size_t)c * N * N * N + y * N + z;
+    sfor<N>([&](auto I) {
+        constexpr int x = decltype(I)::value;
+        T prod = v[x].x * v[x].y;
+        q[x * N * N] = first ? prod : q[x * N * N] + prod;
+    });
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void g_finish(const T* __restrict__ acc, const double* f,
+                                                double* __restrict__ q_out, double* f_out, double dt,
+                                                GridConst gc) {
+    __shared__ double red[5 * 4];
+    __shared__ double lam_s[5];
+    const int c = blockIdx.x;
+    constexpr int NN = N * N * N;
+    const T* q = acc + (size_t)c * NN;
+    double m[5] = {0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < NN; i += 256) {
+        const int z = i % N, y = (i / N) % N, x = i / (N * N);
+        const Basis b = basis_at(gc, x, y, z);
+        const double qv = (double)q[i];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) m[a] = fma(qv, b.p[a], m[a]);
+    }
+    block_sum5<256>(m, red);
+    if (threadIdx.x == 0) {
+        double lam[5];
+        solve5(gc, m, lam);
+        for (int a = 0; a < 5; ++a) lam_s[a] = lam[a];
+    }
+    __syncthreads();
+    double lam[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) lam[a] = lam_s[a];
+    const size_t base = (size_t)c * NN;
+    for (int i = threadIdx.x; i < NN; i += 256) {
+        const int z = i % N, y = (i / N) % N, x = i / (N * N);
+        const double qc = (double)q[i] - correction(lam, basis_at(gc, x, y, z));
+        if (q_out) q_out[base + i] = qc;
+        if (f_out) f_out[base + i] = fma(dt, qc, f[base + i]);
+    }
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+template <typename T, int N>
+hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
+    constexpr int H = (N / 2 + 1) * N * N;
+    constexpr size_t NN = (size_t)N * N * N;
+    const int chunk = (int)std::min<int64_t>(s.ncell, kChunk);
+    char* base = (char*)ws;
+    cx<T>* fh = (cx<T>*)base;
+    cx<T>* work = (cx<T>*)(base + align256((size_t)chunk * H * sizeof(cx<T>)));
+    T* acc = (T*)((char*)work + align256((size_t)chunk * NN * sizeof(cx<T>)));
+    const cx<T>* tab = Tab<T>::get(p);
+    const int bs = 128;
+    for (int64_t c0 = 0; c0 < s.ncell; c0 += chunk) {
+        const int C = (int)std::min<int64_t>(chunk, s.ncell - c0);
+        const unsigned grid = (unsigned)((C * N * N + bs - 1) / bs);
+        const double* f = s.f + c0 * (int64_t)NN;
+        g_fwd_x<T, N><<<grid, bs, 0, st>>>(f, work, C);
+        g_pass_y<T, N, -1><<<grid, bs, 0, st>>>(work, C);
+        g_fwd_z<T, N><<<grid, bs, 0, st>>>(work, fh, C);
+        for (int j = 0; j < p->J; ++j) {
+            g_inv_z<T, N><<<grid, bs, 0, st>>>(fh, tab + (size_t)j * H, work, C);
+            g_pass_y<T, N, 1><<<grid, bs, 0, st>>>(work, C);
+            g_inv_x<T, N><<<grid, bs, 0, st>>>(work, acc, C, j == 0 ? 1 : 0);
+        }
+        g_finish<T, N><<<C, 256, 0, st>>>(acc, f, s.q_out ? s.q_out + c0 * (int64_t)NN : nullptr,
+                                          s.f_out ? s.f_out + c0 * (int64_t)NN : nullptr, s.dt_over_tau, p->gc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t dispatch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
+    switch (p->desc.n) {
+        case 4: return run<T, 4>(p, s, ws, st);
+        case 6: return run<T, 6>(p, s, ws, st);
+        case 8: return run<T, 8>(p, s, ws, st);
+        case 12: return run<T, 12>(p, s, ws, st);
+        case 16: return run<T, 16>(p, s, ws, st);
+        case 24: return run<T, 24>(p, s, ws, st);
+        case 32: return run<T, 32>(p, s, ws, st);
+        case 48: return run<T, 48>(p, s, ws, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t generic_workspace_bytes(const fks_plan* p, int64_t ncell) {
+    const int n = p->desc.n;
+    const int chunk = (int)std::min<int64_t>(ncell, kChunk);
+    size_t H = (size_t)(n / 2 + 1) * n * n, NN = (size_t)n * n * n;
+    if (p->desc.precision == FKS_PREC_F64)
+        return align256(chunk * H * sizeof(cx<double>)) + align256(chunk * NN * sizeof(cx<double>)) +
+               align256(chunk * NN * sizeof(double));
+    return align256(chunk * H * sizeof(cx<float>)) + align256(chunk * NN * sizeof(cx<float>)) +
+           align256(chunk * NN * sizeof(float));
+}
+
+hipError_t collide_generic(const fks_plan* p, const fks_segment& s, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (ws_bytes < generic_workspace_bytes(p, s.ncell)) return hipErrorInvalidValue;
+    if (p->desc.precision == FKS_PREC_F64) return dispatch<double>(p, s, ws, st);
+    return dispatch<float>(p, s, ws, st);
+}
+
+}  // namespace fks

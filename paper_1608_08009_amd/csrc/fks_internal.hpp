@@ -1,0 +1,79 @@
+// Internal declarations shared by the C ABI (fks_abi.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/fks.h"
+
+namespace fks {
+
+// Grid constants used by the FP64 conservation step.  The invariants are taken
+// in the scaled basis phi = (1, v_x/T, v_y/T, v_z/T, |v|^2/T^2); the projector
+// C^T (C C^T)^{-1} C does not depend on an invertible change of basis.
+struct GridConst {
+    double T;         // half box
+    double dv;        // grid step 2T/n
+    double ginv[25];  // inverse Gram matrix of the scaled basis over the grid (row-major)
+};
+
+// Integer velocity-index shifts of one transport step (per axis, per 1D index).
+struct ShiftTable {
+    int8_t s[3][64];
+};
+
+}  // namespace fks
+
+struct fks_plan {
+    fks_plan_desc desc;      // with defaults resolved
+    int M = 0, K = 0, J = 0; // directions, radial terms, convolution terms (M*K + 1)
+    int H = 0;               // half-spectrum points (n/2+1) n^2
+    double kappa = 0.0;      // pi / T
+    fks::GridConst gc{};
+    std::vector<double> dirs;       // [M][4] (e_x, e_y, e_z, w)
+    std::vector<double> rad_nodes;  // [nq]       (empty for the hard-sphere closed form)
+    std::vector<double> rad_coef;   // [nq][K]
+    double* d_tab64 = nullptr;      // [J][H][2] (omega*alpha, beta) FP64
+    float* d_tab32 = nullptr;       // same, rounded to FP32 (FP32 plans only)
+    fks::GridConst* d_gc = nullptr; // device copy of gc
+    size_t table_bytes = 0;
+    bool fused = false;             // fks_collide_batch uses the fused kernel
+    int fused_grid = 0;             // persistent grid of the fused kernel
+    double flops_per_cell = 0.0;
+    int device = 0;
+};
+
+namespace fks {
+
+// host math (fks_abi.hip)
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+int radial_expansion(double gamma, double R, int K, double tol, int nq, std::vector<double>& nodes,
+                     std::vector<double>& coef);
+bool supported_n(int n);
+
+// tables (fks_tables.hip)
+hipError_t build_tables(fks_plan* plan, hipStream_t stream);
+
+// multi-pass path, FP64 and FP32 (fks_generic.hip)
+size_t generic_workspace_bytes(const fks_plan* plan, int64_t ncell);
+hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+// fused single-kernel FP32 path (fks_fused.hip)
+bool fused_available(int n);
+int fused_grid_size(int n, int device);
+size_t fused_workspace_bytes(const fks_plan* plan, int64_t ncell);
+hipError_t collide_fused(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+// moments, projection, transport (fks_aux.hip)
+GridConst grid_const(int n, double T);
+hipError_t moments(const double* f, int64_t ncell, int n, double T, double* U, hipStream_t stream);
+hipError_t conserve(double* f, const double* U, int64_t ncell, int n, double T, hipStream_t stream);
+hipError_t transport(const double* f_in, double* f_out, const fks_space_desc& sp, int n,
+                     const ShiftTable& shift, const double* bc_f, hipStream_t stream);
+
+}  // namespace fks

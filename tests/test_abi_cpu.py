@@ -1,0 +1,81 @@
+"""Host-side checks of libfks.so that need no GPU: loading, exported symbols,
+descriptor validation, and the FP64 host precompute against the oracle."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1608_08009_amd as fks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "fks.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fks_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fks.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 13
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(fks.EXPORTED) == set(declared)
+
+
+def test_status_strings():
+    L = fks.lib()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert L.fks_status_string(s).decode().startswith("FKS_")
+
+
+@pytest.mark.parametrize("field,value,expect", [
+    ("n", 7, fks.FKS_ERR_UNSUPPORTED), ("n", 10, fks.FKS_ERR_UNSUPPORTED), ("n", 64, fks.FKS_ERR_UNSUPPORTED),
+    ("n", 0, fks.FKS_ERR_INVALID), ("T", -1.0, fks.FKS_ERR_INVALID), ("T", float("nan"), fks.FKS_ERR_INVALID),
+    ("gamma", 1.5, fks.FKS_ERR_INVALID), ("n_polar", 0, fks.FKS_ERR_INVALID), ("rule", 5, fks.FKS_ERR_INVALID),
+    ("precision", 9, fks.FKS_ERR_INVALID), ("flags", 0x80, fks.FKS_ERR_INVALID),
+    ("radial_terms", -1, fks.FKS_ERR_INVALID),
+])
+def test_desc_validation_rejects(field, value, expect):
+    d = fks.Desc(n=16, T=8.0)
+    setattr(d, field, value)
+    assert fks.desc_validate(d) == expect
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 12, 16, 24, 32, 48])
+def test_desc_validation_accepts_supported_sizes(n):
+    assert fks.desc_validate(fks.Desc(n=n, T=8.0, gamma=0.5)) == fks.FKS_OK
+
+
+@pytest.mark.parametrize("rule,name", [(fks.RULE_GAUSS, "gauss"), (fks.RULE_MIDPOINT, "midpoint")])
+@pytest.mark.parametrize("npol,naz", [(1, 1), (4, 3), (8, 4), (8, 8), (16, 4)])
+def test_host_sphere_rule_matches_oracle(rule, name, npol, naz):
+    got = fks.host_sphere_rule(npol, naz, rule)
+    e, w = O.sphere_rule(npol, naz, name)
+    assert np.allclose(got[:, :3], e, atol=2e-15, rtol=0)
+    assert np.allclose(got[:, 3], w, atol=2e-15, rtol=0)
+
+
+@pytest.mark.parametrize("gamma,K", [(0.0, 11), (0.5, 7), (0.0, 4)])
+def test_host_radial_terms_match_oracle(gamma, K):
+    R = 3.6
+    k, nodes, coef = fks.host_radial_terms(gamma, R, K=K)
+    rt = O.radial_terms(gamma, R, K=K)
+    assert k == rt.K == K
+    assert np.allclose(nodes, rt.nodes, rtol=1e-14, atol=0)
+    # eigenvector signs are arbitrary; compare the sign-invariant outer products
+    for r in range(K):
+        a, b = coef[:, r], rt.coef[:, r]
+        sgn = np.sign(a @ b)
+        assert np.max(np.abs(a - sgn * b)) < 1e-9 * np.max(np.abs(b)) * max(1.0, 10.0 ** r / 1e3)
+
+
+def test_host_radial_terms_tolerance_selects_K():
+    for gamma in (0.0, 0.5):
+        k, _, _ = fks.host_radial_terms(gamma, 3.6, K=0, tol=1e-4)
+        assert k == O.radial_terms(gamma, 3.6, tol=1e-4).K
