@@ -1,28 +1,35 @@
 // Fused FP32 collision kernel with FP64 conservation fix (one launch per batch).
 //
-// One workgroup owns one cell at a time (persistent loop over cells) and keeps
-// the whole n^3 complex working set of a transform on chip: every thread holds
-// P pencils of n complex values in registers, and the two transposes of each
-// 3D transform go through LDS.  Per cell:
+// Work decomposition: two workgroups on the same XCD form a pair and share
+// each of their cells; each workgroup evaluates half of the convolution terms
+// of the cell (persistent loop over the pair's cells).  Both compute the
+// forward transform and store the identical half spectrum in the cell's slot,
+// which the pair then re-reads once per term from the XCD's L2.  The
+// workgroup that finishes a cell last (atomic counter, no waiting) adds its
+// partner's partial sum and applies the FP64 fix.  Per cell and workgroup:
 //   1. f (FP64, HBM) -> FP32, forward 3D FFT, scale n^-3, zero the Nyquist
-//      planes, store the half spectrum kz in [0, n/2] in a per-workgroup slot
-//      (L2-resident workspace)                                      (eq. FC)
-//   2. for each term j (M*K gain terms, then the loss term (-L, 1)):
+//      planes, store the half spectrum kz in [0, n/2) (eq. FC)
+//   2. for each of its terms j (M*K gain terms, then the loss term (-L, 1)):
 //      Z = (a_j + i b_j) fhat (mirror + conjugate for kz > n/2), inverse 3D
-//      FFT, Q += Re(z) Im(z) in registers                          (eq. ode, fast form)
-//   3. FP64: moments of Q, lambda = G^{-1} C Q, Q_c = Q - C^T lambda,
-//      q_out = Q_c and/or f_out = f + dt/tau Q_c                   (eqs. minim1, f_coll)
+//      FFT, Q += Re(z) Im(z) in registers (eq. ode, fast form)
+//   3. publish the partial Q or, if last, add the partner's and run the FP64
+//      projection: lambda = G^{-1} C Q, Q_c = Q - C^T lambda, q_out = Q_c and/or
+//      f_out = f + dt/tau Q_c (eqs. minim1, f_coll)
 //
 // Thread layouts (t = hi * n + lo, hi in [0, n/P), HP = n/P; pencil p in [0, P)):
 //   C: pencil (y = hi + HP p, z = lo), registers over x      (physical side)
-//   B: pencil (kx = hi + HP p, z = lo), registers over y
-//   A: pencil (kx = hi + HP p, ky = lo), registers over kz   (spectral side)
+//   B: pencil (kx = kx_p, z = lo), registers over y
+//   A: pencil (kx_p, ky_p), registers over kz                 (spectral side)
+// With P = 2 a thread owns the mirrored pencils (kx, ky) and (-kx, -ky), so the
+// tables and fhat (even and Hermitian in k) are loaded once per term for both;
+// for hi = 0 the second pencil is the Nyquist pencil kx = n/2, which is zero.
 // LDS holds HP blocks of n rows with row stride n+1 (padding against bank
 // conflicts; every LDS access is a per-thread base plus an immediate offset).
 // A <-> B only swaps (lane, register) inside the n threads sharing hi: it goes
-// through that group's own block and needs no workgroup barrier.  B <-> C
-// crosses waves: P rounds of n^3/P^2 values with workgroup barriers; in round
-// r each group reads back only its own block, so the next group-local
+// through that group's own block (row = the pencil's ky, column = z) and needs
+// no workgroup barrier.  B <-> C
+// crosses waves: P rounds of n^3/P^2 values with workgroup barriers; in every
+// round each group reads back only its own block, so the next group-local
 // exchange can reuse that block without a barrier.
 #include <hip/hip_runtime.h>
 
@@ -58,30 +65,77 @@ __device__ __forceinline__ V opaque(V v) {
 __device__ __forceinline__ cx<float> cmulf(cx<float> a, cx<float> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
+// a * conj(b)
+__device__ __forceinline__ cx<float> cmulf_conj(cx<float> a, cx<float> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// spectral pencil (kx, ky) owned by thread (hi, lo) as pencil p
+template <int N, int P>
+__device__ __forceinline__ int kx_of(int p, int hi) {
+    if (P == 1 || p == 0) return hi;
+    return hi == 0 ? N / 2 : N - hi;
+}
+template <int N, int P>
+__device__ __forceinline__ int ky_of(int p, int hi, int lo) {
+    if (P == 1 || p == 0 || hi == 0) return lo;
+    return (N - lo) & (N - 1);
+}
+// forward C -> B, round r: LDS block receiving spectral row x (the reader's hi)
+template <int N, int P, int R, int X>
+constexpr int fwd_block() {
+    if constexpr (R == 0) return X;
+    else return X == N / 2 ? 0 : N - X;
+}
+
+struct FusedArgs {
+    const double* f;
+    double* q_out;
+    double* f_out;
+    int64_t ncell;
+    double dt;
+    const cx<float>* tab;   // [J][(n/2+1) n n] balanced (a, b)
+    int J;
+    int npairs;
+    cx<float>* fh;          // [ncell][n/2][n][n]
+    float* part;            // [ncell][2][n^3]
+    int* cnt;               // [ncell]
+    const GridConst* gc;
+};
+
+__global__ void k_zero_counters(int* cnt, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        cnt[i] = 0;
+}
 
 template <int N>
-__global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(const double* f, double* __restrict__ q_out,
-                                                            double* f_out, int64_t ncell, double dt,
-                                                            const cx<float>* __restrict__ tab, int J,
-                                                            cx<float>* __restrict__ fh_ws,
-                                                            const GridConst* __restrict__ gcp) {
+__global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(FusedArgs A) {
     constexpr int P = Cfg<N>::P;
     constexpr int NT = N * N / P;
     constexpr int HP = N / P;
     constexpr int NN = N * N;
+    constexpr int N3 = N * N * N;
     constexpr int RS = N + 1;        // LDS row stride (complex)
     constexpr int BS = N * RS;       // LDS block stride
-    constexpr int H = (N / 2 + 1) * N * N;
+    constexpr int H = (N / 2 + 1) * N * N;   // table stride per term
+    constexpr int HS = (N / 2) * N * N;      // spectrum slot per cell
     __shared__ cx<float> lds[HP * BS];
     __shared__ double red[5 * (NT / 64 > 0 ? NT / 64 : 1)];
+    __shared__ int s_flag;
 
     const int t = threadIdx.x;
     const int hi = t / N, lo = t % N;
     cx<float>* const blk = lds + hi * BS;   // this group's block
-    cx<float>* const fh = fh_ws + (size_t)blockIdx.x * H;
+    // pairs of workgroups on one XCD: blocks b and b ^ 8
+    const int b = blockIdx.x;
+    const int half = (b >> 3) & 1;
+    const int pair = (b & 7) | ((b >> 4) << 3);
+    const int J0 = (A.J + 1) / 2;
+    const int j_begin = half ? J0 : 0, j_end = half ? A.J : J0;
 
-    for (int64_t cell = blockIdx.x; cell < ncell; cell += gridDim.x) {
-        const double* fc = f + cell * (int64_t)(NN * N);
+    for (int64_t cell = pair; cell < A.ncell; cell += A.npairs) {
+        const double* fc = A.f + cell * (int64_t)N3;
+        cx<float>* const fh = A.fh + cell * (int64_t)HS;
 
         // ---------------- forward transform ----------------
         cx<float> c[P][N];
@@ -94,86 +148,92 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(const double* f, do
             });
             fft<float, N, -1>(c[p]);
         });
-        cx<float> b[P][N];
-        sfor<P>([&](auto rI) {   // C -> B, round r delivers B-pencil r (kx in [HP r, HP r + HP))
+        cx<float> bb[P][N];
+        sfor<P>([&](auto rI) {   // C -> B, round r delivers B-pencil r
             constexpr int r = decltype(rI)::value;
             __syncthreads();
             sfor<P>([&](auto pI) {
                 constexpr int p = decltype(pI)::value;
                 cx<float>* dst = lds + (hi + HP * p) * RS + lo;   // row y, column z
                 sfor<HP>([&](auto xI) {
-                    constexpr int xx = decltype(xI)::value;
-                    dst[xx * BS] = c[p][HP * r + xx];
+                    constexpr int x = HP * r + decltype(xI)::value;
+                    dst[fwd_block<N, P, r, x>() * BS] = c[p][x];
                 });
             });
             __syncthreads();
             sfor<N>([&](auto yI) {
                 constexpr int y = decltype(yI)::value;
-                b[r][y] = blk[y * RS + lo];
+                bb[r][y] = blk[y * RS + lo];
             });
         });
-        cx<float> a[P][N];
         sfor<P>([&](auto pI) {
             constexpr int p = decltype(pI)::value;
-            fft<float, N, -1>(b[p]);
+            fft<float, N, -1>(bb[p]);
             // B -> A inside the group: element (row ky, column z)
             sfor<N>([&](auto kI) {
                 constexpr int ky = decltype(kI)::value;
-                blk[ky * RS + lo] = b[p][ky];
+                blk[ky * RS + lo] = bb[p][ky];
             });
             wave_sync();
+            cx<float> a[N];
+            const cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // this pencil's actual ky
             sfor<N>([&](auto zI) {
                 constexpr int z = decltype(zI)::value;
-                a[p][z] = blk[lo * RS + z];
+                a[z] = arow[z];
             });
             wave_sync();
-            fft<float, N, -1>(a[p]);
-            const int kx = hi + HP * p;
-            const float s = ((kx == N / 2) || (lo == N / 2)) ? 0.0f : 1.0f / (float)(N * N * N);
-            cx<float>* o = fh + opaque(kx * N + lo);
+            fft<float, N, -1>(a);
+            const int kx = kx_of<N, P>(p, hi), ky = ky_of<N, P>(p, hi, lo);
+            const float s = ((kx == N / 2) || (ky == N / 2)) ? 0.0f : 1.0f / (float)N3;
+            cx<float>* o = fh + opaque(kx * N + ky);
             sfor<N / 2>([&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
-                o[kz * NN] = cx<float>{a[p][kz].x * s, a[p][kz].y * s};
+                o[kz * NN] = cx<float>{a[kz].x * s, a[kz].y * s};
             });
-            o[(N / 2) * NN] = cx<float>{0.0f, 0.0f};
         });
         __threadfence_block();
         __syncthreads();
 
-        // ---------------- terms ----------------
+        // ---------------- this workgroup's terms ----------------
         float q[P][N];
         sfor<P>([&](auto pI) {
             constexpr int p = decltype(pI)::value;
             sfor<N>([&](auto xI) { q[p][decltype(xI)::value] = 0.0f; });
         });
-        for (int j = 0; j < J; ++j) {
-            const cx<float>* tj = tab + (size_t)j * H;
+        for (int j = j_begin; j < j_end; ++j) {
+            const cx<float>* tj = A.tab + (size_t)j * H;
             cx<float> za[P][N];
-            sfor<P>([&](auto pI) {
-                constexpr int p = decltype(pI)::value;
-                const int kx = hi + HP * p;
-                const int o1 = opaque(kx * N + lo);
-                const int o2 = opaque(((N - kx) & (N - 1)) * N + ((N - lo) & (N - 1)));
-                sfor<N>([&](auto kI) {
-                    constexpr int kz = decltype(kI)::value;
-                    if constexpr (kz <= N / 2) {
-                        const int h = o1 + kz * NN;
-                        za[p][kz] = cmulf(tj[h], fh[h]);
-                    } else {
-                        const int h = o2 + (N - kz) * NN;
-                        cx<float> g = fh[h];
-                        g.y = -g.y;
-                        za[p][kz] = cmulf(tj[h], g);
-                    }
-                });
-                fft<float, N, 1>(za[p]);
+            // positions: own pencil (hi, lo) and its mirror (-hi, -lo); kz in [0, n/2)
+            const int oa = opaque(hi * N + lo);
+            const int ob = opaque(((N - hi) & (N - 1)) * N + ((N - lo) & (N - 1)));
+            sfor<N / 2>([&](auto kI) {
+                constexpr int kz = decltype(kI)::value;
+                const cx<float> ta = tj[oa + kz * NN], fa = fh[oa + kz * NN];
+                const cx<float> tb = tj[ob + kz * NN], fb = fh[ob + kz * NN];
+                // pencil 0 = (hi, lo): kz from (hi, lo); -kz from the mirror (conjugated)
+                za[0][kz] = cmulf(ta, fa);
+                if constexpr (kz > 0) za[0][N - kz] = cmulf_conj(tb, fb);
+                if constexpr (P == 2) {
+                    // pencil 1 = (-hi, -lo): kz from the mirror, -kz from (hi, lo)
+                    za[1][kz] = cmulf(tb, fb);
+                    if constexpr (kz > 0) za[1][N - kz] = cmulf_conj(ta, fa);
+                }
             });
+            za[0][N / 2] = cx<float>{0.0f, 0.0f};
+            if constexpr (P == 2) {
+                za[1][N / 2] = cx<float>{0.0f, 0.0f};
+                if (hi == 0) {   // second pencil of hi = 0 is the (zero) Nyquist pencil kx = n/2
+                    sfor<N>([&](auto kI) { za[1][decltype(kI)::value] = cx<float>{0.0f, 0.0f}; });
+                }
+            }
             cx<float> zb[P][N];
-            sfor<P>([&](auto pI) {   // A -> B inside the group
+            sfor<P>([&](auto pI) {   // z transform, then A -> B inside the group
                 constexpr int p = decltype(pI)::value;
+                fft<float, N, 1>(za[p]);
+                cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // row = this pencil's actual ky
                 sfor<N>([&](auto zI) {
                     constexpr int z = decltype(zI)::value;
-                    blk[lo * RS + z] = za[p][z];
+                    arow[z] = za[p][z];
                 });
                 wave_sync();
                 sfor<N>([&](auto kI) {
@@ -189,7 +249,7 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(const double* f, do
                 __syncthreads();
                 sfor<P>([&](auto pI) {
                     constexpr int p = decltype(pI)::value;
-                    cx<float>* dst = lds + (hi + HP * p) * RS + lo;   // row kx, column z
+                    cx<float>* dst = lds + kx_of<N, P>(p, hi) * RS + lo;   // row kx, column z
                     sfor<HP>([&](auto yI) {
                         constexpr int yy = decltype(yI)::value;
                         dst[yy * BS] = zb[p][HP * r + yy];
@@ -211,57 +271,93 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(const double* f, do
             });
         }
 
-        // ---------------- FP64 projection and update ----------------
-        // scaled invariants (1, vx/T, vy/T, vz/T, |v|^2/T^2); the grid step is
-        // made opaque so the per-node coordinates are not hoisted out of the
-        // cell loop into long-lived registers
-        const double h = opaque(gcp->dv / gcp->T);
-        const double uz = -1.0 + lo * h;
-        double m[5] = {0, 0, 0, 0, 0};
-        sfor<P>([&](auto pI) {
-            constexpr int p = decltype(pI)::value;
-            const double uy = -1.0 + (hi + HP * p) * h;
-            const double r2 = uy * uy + uz * uz;
-            sfor<N>([&](auto xI) {
-                constexpr int x = decltype(xI)::value;
-                const double ux = -1.0 + x * h;
-                const double qv = (double)q[p][x];
-                m[0] += qv;
-                m[1] = fma(qv, ux, m[1]);
-                m[2] = fma(qv, uy, m[2]);
-                m[3] = fma(qv, uz, m[3]);
-                m[4] = fma(qv, fma(ux, ux, r2), m[4]);
-            });
-        });
-        block_sum5<NT>(m, red);
-        double lam[5];
-        solve5(*gcp, m, lam);
-        const int64_t base = cell * (int64_t)(NN * N);
-        sfor<P>([&](auto pI) {
-            constexpr int p = decltype(pI)::value;
-            const double uy = -1.0 + (hi + HP * p) * h;
-            const double r2 = uy * uy + uz * uz;
-            const double l0 = lam[0] + lam[2] * uy + lam[3] * uz + lam[4] * r2;
-            const int64_t off = base + opaque((hi + HP * p) * N + lo);
-            double qc[N];
-            sfor<N>([&](auto xI) {
-                constexpr int x = decltype(xI)::value;
-                const double ux = -1.0 + x * h;
-                qc[x] = (double)q[p][x] - fma(lam[4], ux * ux, fma(lam[1], ux, l0));
-            });
-            if (q_out) {
+        // ---------------- pair hand-off ----------------
+        // partial sums live in C layout: value (x, y = hi + HP p, z = lo)
+        if (t == 0) s_flag = __hip_atomic_load(A.cnt + cell, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        bool last = s_flag == 1;     // partner already published its partial
+        if (!last) {
+            float* mine = A.part + (cell * 2 + half) * (int64_t)N3;
+            sfor<P>([&](auto pI) {
+                constexpr int p = decltype(pI)::value;
+                float* o = mine + opaque((hi + HP * p) * N + lo);
                 sfor<N>([&](auto xI) {
                     constexpr int x = decltype(xI)::value;
-                    q_out[off + x * NN] = qc[x];
+                    o[x * NN] = q[p][x];
                 });
-            }
-            if (f_out) {
+            });
+            __threadfence();
+            __syncthreads();
+            if (t == 0) s_flag = atomicAdd(A.cnt + cell, 1);
+            __syncthreads();
+            last = s_flag == 1;
+        }
+        if (last) {
+            __threadfence();
+            const float* other = A.part + (cell * 2 + (1 - half)) * (int64_t)N3;
+            sfor<P>([&](auto pI) {
+                constexpr int p = decltype(pI)::value;
+                const float* o = other + opaque((hi + HP * p) * N + lo);
                 sfor<N>([&](auto xI) {
                     constexpr int x = decltype(xI)::value;
-                    f_out[off + x * NN] = fma(dt, qc[x], f[off + x * NN]);
+                    q[p][x] += o[x * NN];
                 });
-            }
-        });
+            });
+            if (t == 0) A.cnt[cell] = 0;   // ready for the next call
+
+            // ---------------- FP64 projection and update ----------------
+            // scaled invariants (1, vx/T, vy/T, vz/T, |v|^2/T^2); the grid step is
+            // opaque so the per-node coordinates are not hoisted out of the cell
+            // loop into long-lived registers
+            const double h = opaque(A.gc->dv / A.gc->T);
+            const double uz = -1.0 + lo * h;
+            double m[5] = {0, 0, 0, 0, 0};
+            sfor<P>([&](auto pI) {
+                constexpr int p = decltype(pI)::value;
+                const double uy = -1.0 + (hi + HP * p) * h;
+                const double r2 = uy * uy + uz * uz;
+                sfor<N>([&](auto xI) {
+                    constexpr int x = decltype(xI)::value;
+                    const double ux = -1.0 + x * h;
+                    const double qv = (double)q[p][x];
+                    m[0] += qv;
+                    m[1] = fma(qv, ux, m[1]);
+                    m[2] = fma(qv, uy, m[2]);
+                    m[3] = fma(qv, uz, m[3]);
+                    m[4] = fma(qv, fma(ux, ux, r2), m[4]);
+                });
+            });
+            block_sum5<NT>(m, red);
+            double lam[5];
+            solve5(*A.gc, m, lam);
+            const int64_t base = cell * (int64_t)N3;
+            sfor<P>([&](auto pI) {
+                constexpr int p = decltype(pI)::value;
+                const double uy = -1.0 + (hi + HP * p) * h;
+                const double r2 = uy * uy + uz * uz;
+                const double l0 = lam[0] + lam[2] * uy + lam[3] * uz + lam[4] * r2;
+                const int64_t off = base + opaque((hi + HP * p) * N + lo);
+                double qc[N];
+                sfor<N>([&](auto xI) {
+                    constexpr int x = decltype(xI)::value;
+                    const double ux = -1.0 + x * h;
+                    qc[x] = (double)q[p][x] - fma(lam[4], ux * ux, fma(lam[1], ux, l0));
+                });
+                if (A.q_out) {
+                    sfor<N>([&](auto xI) {
+                        constexpr int x = decltype(xI)::value;
+                        A.q_out[off + x * NN] = qc[x];
+                    });
+                }
+                if (A.f_out) {
+                    sfor<N>([&](auto xI) {
+                        constexpr int x = decltype(xI)::value;
+                        A.f_out[off + x * NN] = fma(A.dt, qc[x], A.f[off + x * NN]);
+                    });
+                }
+            });
+        }
+        __syncthreads();
     }
 }
 
@@ -273,16 +369,53 @@ int grid_for(int device) {
     int per = 0;
     constexpr int NT = N * N / Cfg<N>::P;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_fused<N>, NT, 0) != hipSuccess || per <= 0) per = 1;
-    return cus * per;
+    int g = cus * per;
+    return std::max(16, (g / 16) * 16);   // whole XCD pairs: multiple of 16 workgroups
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t fh, part, cnt, total;
+};
+inline WsLayout ws_layout(int n, int64_t ncell) {
+    WsLayout w{};
+    const size_t n3 = (size_t)n * n * n;
+    w.fh = 0;
+    w.part = align256((size_t)ncell * (n / 2) * n * n * sizeof(cx<float>));
+    w.cnt = w.part + align256((size_t)ncell * 2 * n3 * sizeof(float));
+    w.total = w.cnt + align256((size_t)ncell * sizeof(int));
+    return w;
+}
+
+// pairs of workgroups actually launched: a multiple of 8, at most grid/2
+inline int npairs_for(const fks_plan* p, int64_t ncell) {
+    const int maxp = p->fused_grid / 2;
+    int64_t want = std::min<int64_t>(ncell, maxp);
+    return (int)std::max<int64_t>(8, ((want + 7) / 8) * 8 > maxp ? (maxp / 8) * 8 : ((want + 7) / 8) * 8);
 }
 
 template <int N>
 hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
     constexpr int NT = N * N / Cfg<N>::P;
-    const int64_t grid = std::min<int64_t>(s.ncell, p->fused_grid);
-    k_fused<N><<<(unsigned)grid, NT, 0, st>>>(s.f, s.q_out, s.f_out, s.ncell, s.dt_over_tau,
-                                             reinterpret_cast<const cx<float>*>(p->d_tab32), p->J,
-                                             reinterpret_cast<cx<float>*>(ws), p->d_gc);
+    const WsLayout w = ws_layout(N, s.ncell);
+    char* base = (char*)ws;
+    FusedArgs a{};
+    a.f = s.f;
+    a.q_out = s.q_out;
+    a.f_out = s.f_out;
+    a.ncell = s.ncell;
+    a.dt = s.dt_over_tau;
+    a.tab = reinterpret_cast<const cx<float>*>(p->d_tab32);
+    a.J = p->J;
+    a.npairs = npairs_for(p, s.ncell);
+    a.fh = reinterpret_cast<cx<float>*>(base + w.fh);
+    a.part = reinterpret_cast<float*>(base + w.part);
+    a.cnt = reinterpret_cast<int*>(base + w.cnt);
+    a.gc = p->d_gc;
+    const int64_t zb = std::min<int64_t>((s.ncell + 255) / 256, 1024);
+    k_zero_counters<<<(unsigned)zb, 256, 0, st>>>(a.cnt, s.ncell);
+    k_fused<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -299,11 +432,7 @@ int fused_grid_size(int n, int device) {
     }
 }
 
-size_t fused_workspace_bytes(const fks_plan* p, int64_t ncell) {
-    const int n = p->desc.n;
-    const int64_t grid = std::min<int64_t>(ncell, p->fused_grid);
-    return (size_t)grid * (size_t)(n / 2 + 1) * n * n * sizeof(cx<float>);
-}
+size_t fused_workspace_bytes(const fks_plan* p, int64_t ncell) { return ws_layout(p->desc.n, ncell).total; }
 
 hipError_t collide_fused(const fks_plan* p, const fks_segment& s, void* ws, size_t ws_bytes, hipStream_t st) {
     if (ws_bytes < fused_workspace_bytes(p, s.ncell)) return hipErrorInvalidValue;
