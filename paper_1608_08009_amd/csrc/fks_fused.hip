@@ -4,16 +4,19 @@
 // each of their cells; each workgroup evaluates half of the convolution terms
 // of the cell (persistent loop over the pair's cells).  Both compute the
 // forward transform and store the identical half spectrum in the cell's slot,
-// which the pair then re-reads once per term from the XCD's L2.  The
-// workgroup that finishes a cell last (atomic counter, no waiting) adds its
-// partner's partial sum and applies the FP64 fix.  Per cell and workgroup:
+// which the pair then re-reads once per term from the XCD's L2.  Each
+// workgroup writes its partial sum; a second, HBM-bound kernel adds the two
+// partials and applies the FP64 fix (the kernel boundary orders the writes,
+// so no device-scope fence, which would flush the XCD's L2, is needed).
+//   k_terms, per cell and workgroup:
 //   1. f (FP64, HBM) -> FP32, forward 3D FFT, scale n^-3, zero the Nyquist
 //      planes, store the half spectrum kz in [0, n/2) (eq. FC)
 //   2. for each of its terms j (M*K gain terms, then the loss term (-L, 1)):
 //      Z = (a_j + i b_j) fhat (mirror + conjugate for kz > n/2), inverse 3D
 //      FFT, Q += Re(z) Im(z) in registers (eq. ode, fast form)
-//   3. publish the partial Q or, if last, add the partner's and run the FP64
-//      projection: lambda = G^{-1} C Q, Q_c = Q - C^T lambda, q_out = Q_c and/or
+//   3. store the partial Q (FP32)
+//   k_finish, per cell: Q = sum of the two partials, FP64 projection
+//      lambda = G^{-1} C Q, Q_c = Q - C^T lambda, q_out = Q_c and/or
 //      f_out = f + dt/tau Q_c (eqs. minim1, f_coll)
 //
 // Thread layouts (t = hi * n + lo, hi in [0, n/P), HP = n/P; pencil p in [0, P)):
@@ -99,17 +102,11 @@ struct FusedArgs {
     int npairs;
     cx<float>* fh;          // [ncell][n/2][n][n]
     float* part;            // [ncell][2][n^3]
-    int* cnt;               // [ncell]
     const GridConst* gc;
 };
 
-__global__ void k_zero_counters(int* cnt, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        cnt[i] = 0;
-}
-
 template <int N>
-__global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(FusedArgs A) {
+__global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
     constexpr int P = Cfg<N>::P;
     constexpr int NT = N * N / P;
     constexpr int HP = N / P;
@@ -120,8 +117,6 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(FusedArgs A) {
     constexpr int H = (N / 2 + 1) * N * N;   // table stride per term
     constexpr int HS = (N / 2) * N * N;      // spectrum slot per cell
     __shared__ cx<float> lds[HP * BS];
-    __shared__ double red[5 * (NT / 64 > 0 ? NT / 64 : 1)];
-    __shared__ int s_flag;
 
     const int t = threadIdx.x;
     const int hi = t / N, lo = t % N;
@@ -271,93 +266,70 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_fused(FusedArgs A) {
             });
         }
 
-        // ---------------- pair hand-off ----------------
-        // partial sums live in C layout: value (x, y = hi + HP p, z = lo)
-        if (t == 0) s_flag = __hip_atomic_load(A.cnt + cell, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        bool last = s_flag == 1;     // partner already published its partial
-        if (!last) {
-            float* mine = A.part + (cell * 2 + half) * (int64_t)N3;
-            sfor<P>([&](auto pI) {
-                constexpr int p = decltype(pI)::value;
-                float* o = mine + opaque((hi + HP * p) * N + lo);
-                sfor<N>([&](auto xI) {
-                    constexpr int x = decltype(xI)::value;
-                    o[x * NN] = q[p][x];
-                });
+        // ---------------- partial sum (C layout: x, y = hi + HP p, z = lo) ----------------
+        float* mine = A.part + (cell * 2 + half) * (int64_t)N3;
+        sfor<P>([&](auto pI) {
+            constexpr int p = decltype(pI)::value;
+            float* o = mine + opaque((hi + HP * p) * N + lo);
+            sfor<N>([&](auto xI) {
+                constexpr int x = decltype(xI)::value;
+                o[x * NN] = q[p][x];
             });
-            __threadfence();
-            __syncthreads();
-            if (t == 0) s_flag = atomicAdd(A.cnt + cell, 1);
-            __syncthreads();
-            last = s_flag == 1;
-        }
-        if (last) {
-            __threadfence();
-            const float* other = A.part + (cell * 2 + (1 - half)) * (int64_t)N3;
-            sfor<P>([&](auto pI) {
-                constexpr int p = decltype(pI)::value;
-                const float* o = other + opaque((hi + HP * p) * N + lo);
-                sfor<N>([&](auto xI) {
-                    constexpr int x = decltype(xI)::value;
-                    q[p][x] += o[x * NN];
-                });
-            });
-            if (t == 0) A.cnt[cell] = 0;   // ready for the next call
+        });
+    }
+}
 
-            // ---------------- FP64 projection and update ----------------
-            // scaled invariants (1, vx/T, vy/T, vz/T, |v|^2/T^2); the grid step is
-            // opaque so the per-node coordinates are not hoisted out of the cell
-            // loop into long-lived registers
-            const double h = opaque(A.gc->dv / A.gc->T);
-            const double uz = -1.0 + lo * h;
-            double m[5] = {0, 0, 0, 0, 0};
-            sfor<P>([&](auto pI) {
-                constexpr int p = decltype(pI)::value;
-                const double uy = -1.0 + (hi + HP * p) * h;
-                const double r2 = uy * uy + uz * uz;
-                sfor<N>([&](auto xI) {
-                    constexpr int x = decltype(xI)::value;
-                    const double ux = -1.0 + x * h;
-                    const double qv = (double)q[p][x];
-                    m[0] += qv;
-                    m[1] = fma(qv, ux, m[1]);
-                    m[2] = fma(qv, uy, m[2]);
-                    m[3] = fma(qv, uz, m[3]);
-                    m[4] = fma(qv, fma(ux, ux, r2), m[4]);
-                });
-            });
-            block_sum5<NT>(m, red);
-            double lam[5];
-            solve5(*A.gc, m, lam);
-            const int64_t base = cell * (int64_t)N3;
-            sfor<P>([&](auto pI) {
-                constexpr int p = decltype(pI)::value;
-                const double uy = -1.0 + (hi + HP * p) * h;
-                const double r2 = uy * uy + uz * uz;
-                const double l0 = lam[0] + lam[2] * uy + lam[3] * uz + lam[4] * r2;
-                const int64_t off = base + opaque((hi + HP * p) * N + lo);
-                double qc[N];
-                sfor<N>([&](auto xI) {
-                    constexpr int x = decltype(xI)::value;
-                    const double ux = -1.0 + x * h;
-                    qc[x] = (double)q[p][x] - fma(lam[4], ux * ux, fma(lam[1], ux, l0));
-                });
-                if (A.q_out) {
-                    sfor<N>([&](auto xI) {
-                        constexpr int x = decltype(xI)::value;
-                        A.q_out[off + x * NN] = qc[x];
-                    });
-                }
-                if (A.f_out) {
-                    sfor<N>([&](auto xI) {
-                        constexpr int x = decltype(xI)::value;
-                        A.f_out[off + x * NN] = fma(A.dt, qc[x], A.f[off + x * NN]);
-                    });
-                }
-            });
-        }
-        __syncthreads();
+// Sum of the two partials, FP64 projection onto the kernel of the collision
+// invariants and the update; one workgroup per cell, values kept in registers.
+// With FT = min(1024, n^3) threads, thread t owns the nodes t + FT k: its (y, z)
+// are fixed and x advances by FT / n^2 per step.
+template <int N>
+constexpr int finish_threads() { return N * N * N < 1024 ? N * N * N : 1024; }
+
+template <int N>
+__global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
+    constexpr int N3 = N * N * N;
+    constexpr int FT = finish_threads<N>();
+    constexpr int V = N3 / FT;
+    constexpr int XS = FT / (N * N);   // x advance per step
+    __shared__ double red[5 * (FT / 64)];
+    const int t = threadIdx.x;
+    const int64_t cell = blockIdx.x;
+    const float* p0 = A.part + cell * 2 * (int64_t)N3;
+    const float* p1 = p0 + N3;
+    const double h = A.gc->dv / A.gc->T;
+    const int z = t % N, y = (t / N) % N, x0 = t / (N * N);
+    const double uy = -1.0 + y * h, uz = -1.0 + z * h, r2 = uy * uy + uz * uz;
+    double qv[V];
+    double m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int i = t + k * FT;
+        const double ux = -1.0 + (x0 + k * XS) * h;
+        qv[k] = (double)p0[i] + (double)p1[i];
+        m[0] += qv[k];
+        m[1] = fma(qv[k], ux, m[1]);
+        m[2] = fma(qv[k], uy, m[2]);
+        m[3] = fma(qv[k], uz, m[3]);
+        m[4] = fma(qv[k], fma(ux, ux, r2), m[4]);
+    }
+    block_sum5<FT>(m, red);
+    double lam[5];
+    solve5(*A.gc, m, lam);
+    const double l0 = lam[0] + lam[2] * uy + lam[3] * uz + lam[4] * r2;
+    const int64_t base = cell * (int64_t)N3 + t;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const double ux = -1.0 + (x0 + k * XS) * h;
+        qv[k] -= fma(lam[4], ux * ux, fma(lam[1], ux, l0));
+    }
+    if (A.q_out) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) A.q_out[base + k * FT] = qv[k];
+    }
+    if (A.f_out) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) A.f_out[base + k * FT] = fma(A.dt, qv[k], A.f[base + k * FT]);
     }
 }
 
@@ -368,7 +340,7 @@ int grid_for(int device) {
         cus = 256;
     int per = 0;
     constexpr int NT = N * N / Cfg<N>::P;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_fused<N>, NT, 0) != hipSuccess || per <= 0) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_terms<N>, NT, 0) != hipSuccess || per <= 0) per = 1;
     int g = cus * per;
     return std::max(16, (g / 16) * 16);   // whole XCD pairs: multiple of 16 workgroups
 }
@@ -376,15 +348,14 @@ int grid_for(int device) {
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct WsLayout {
-    size_t fh, part, cnt, total;
+    size_t fh, part, total;
 };
 inline WsLayout ws_layout(int n, int64_t ncell) {
     WsLayout w{};
     const size_t n3 = (size_t)n * n * n;
     w.fh = 0;
     w.part = align256((size_t)ncell * (n / 2) * n * n * sizeof(cx<float>));
-    w.cnt = w.part + align256((size_t)ncell * 2 * n3 * sizeof(float));
-    w.total = w.cnt + align256((size_t)ncell * sizeof(int));
+    w.total = w.part + align256((size_t)ncell * 2 * n3 * sizeof(float));
     return w;
 }
 
@@ -411,11 +382,11 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     a.npairs = npairs_for(p, s.ncell);
     a.fh = reinterpret_cast<cx<float>*>(base + w.fh);
     a.part = reinterpret_cast<float*>(base + w.part);
-    a.cnt = reinterpret_cast<int*>(base + w.cnt);
     a.gc = p->d_gc;
-    const int64_t zb = std::min<int64_t>((s.ncell + 255) / 256, 1024);
-    k_zero_counters<<<(unsigned)zb, 256, 0, st>>>(a.cnt, s.ncell);
-    k_fused<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
+    k_terms<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish<N><<<(unsigned)s.ncell, finish_threads<N>(), 0, st>>>(a);
     return hipGetLastError();
 }
 
