@@ -4,7 +4,9 @@
 // each of their cells; each workgroup evaluates half of the convolution terms
 // of the cell (persistent loop over the pair's cells).  Both compute the
 // forward transform and store the identical half spectrum in the cell's slot,
-// which the pair then re-reads once per term from the XCD's L2.  Each
+// which the pair then re-reads once per term from the XCD's L2 (the streaming
+// reads of f and writes of partial sums are non-temporal so that they do not
+// evict the reused spectrum slots and tables).  Each
 // workgroup writes its partial sum; a second, HBM-bound kernel adds the two
 // partials and applies the FP64 fix (the kernel boundary orders the writes,
 // so no device-scope fence, which would flush the XCD's L2, is needed).
@@ -125,10 +127,12 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
     const int b = blockIdx.x;
     const int half = (b >> 3) & 1;
     const int pair = (b & 7) | ((b >> 4) << 3);
-    const int J0 = (A.J + 1) / 2;
-    const int j_begin = half ? J0 : 0, j_end = half ? A.J : J0;
 
-    for (int64_t cell = pair; cell < A.ncell; cell += A.npairs) {
+    for (int64_t cell = pair, it = 0; cell < A.ncell; cell += A.npairs, ++it) {
+        // split the terms in two; for odd J the extra term alternates between
+        // the halves so that the pair stays on the same cell
+        const int J0 = (it & 1) ? A.J / 2 : (A.J + 1) / 2;
+        const int j_begin = half ? J0 : 0, j_end = half ? A.J : J0;
         const double* fc = A.f + cell * (int64_t)N3;
         cx<float>* const fh = A.fh + cell * (int64_t)HS;
 
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             const double* src = fc + opaque((hi + HP * p) * N + lo);
             sfor<N>([&](auto xI) {
                 constexpr int x = decltype(xI)::value;
-                c[p][x] = cx<float>{(float)src[x * NN], 0.0f};
+                c[p][x] = cx<float>{(float)__builtin_nontemporal_load(src + x * NN), 0.0f};
             });
             fft<float, N, -1>(c[p]);
         });
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             float* o = mine + opaque((hi + HP * p) * N + lo);
             sfor<N>([&](auto xI) {
                 constexpr int x = decltype(xI)::value;
-                o[x * NN] = q[p][x];
+                __builtin_nontemporal_store(q[p][x], o + x * NN);
             });
         });
     }
@@ -306,7 +310,7 @@ __global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
     for (int k = 0; k < V; ++k) {
         const int i = t + k * FT;
         const double ux = -1.0 + (x0 + k * XS) * h;
-        qv[k] = (double)p0[i] + (double)p1[i];
+        qv[k] = (double)__builtin_nontemporal_load(p0 + i) + (double)__builtin_nontemporal_load(p1 + i);
         m[0] += qv[k];
         m[1] = fma(qv[k], ux, m[1]);
         m[2] = fma(qv[k], uy, m[2]);
@@ -325,11 +329,13 @@ __global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
     }
     if (A.q_out) {
 #pragma unroll
-        for (int k = 0; k < V; ++k) A.q_out[base + k * FT] = qv[k];
+        for (int k = 0; k < V; ++k) __builtin_nontemporal_store(qv[k], A.q_out + base + k * FT);
     }
     if (A.f_out) {
 #pragma unroll
-        for (int k = 0; k < V; ++k) A.f_out[base + k * FT] = fma(A.dt, qv[k], A.f[base + k * FT]);
+        for (int k = 0; k < V; ++k)
+            __builtin_nontemporal_store(fma(A.dt, qv[k], __builtin_nontemporal_load(A.f + base + k * FT)),
+                                        A.f_out + base + k * FT);
     }
 }
 
