@@ -14,6 +14,7 @@ which doubles as a parity check of the timed configuration.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import multiprocessing as mp
@@ -75,6 +76,28 @@ def cpu_baseline(sample_cells, workers):
     }, ref
 
 
+def _fused_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("fks_fused.hip", "fks_fft.hpp", "fks_common.hpp"):
+        with open(os.path.join(ROOT, "paper_1608_08009_amd", "csrc", name), "rb") as fp:
+            h.update(fp.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_per_launch():
+    """HBM bytes per launch of the terms kernel from the committed counter summary,
+    or None if the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_terms32_hs4096.json")
+    try:
+        with open(path) as fp:
+            rec = json.load(fp)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _fused_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +106,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=64, help="cells timed on the CPU oracle (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 512 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,12 +158,30 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
     launch_ms = [a.elapsed_time(b) for a, b in ev]
     ms_per_step = total_ms / args.steps
-    avg_launch_ms = sum(launch_ms) / len(launch_ms)
+    avg_call_ms = sum(launch_ms) / len(launch_ms)
     value = NCELL * N_V ** 3 / (ms_per_step * 1e-3)
+    # per-kernel durations (HIP events recorded by the library on this stream)
+    fks.profile_enable(True)
+    kt = []
+    for i in range(max(3, min(args.steps, 10))):
+        step(fa, fb)
+        fa, fb = fb, fa
+        kt.append(fks.profile_last())
+    fks.profile_enable(False)
+    terms_ms = sum(k[0] for k in kt) / len(kt)
+    finish_ms = sum(k[1] for k in kt) / len(kt)
     flops_launch = plan.info.flops_per_cell * NCELL
-    achieved_tflops = flops_launch / (avg_launch_ms * 1e-3) / 1e12
-    print(f"[bench] fp32+fix: {ms_per_step:.3f} ms/step, kernel {avg_launch_ms:.3f} ms, "
-          f"{achieved_tflops:.1f} TFLOP/s algorithmic", file=sys.stderr, flush=True)
+    achieved_tflops = flops_launch / (terms_ms * 1e-3) / 1e12
+    print(f"[bench] fp32+fix: {ms_per_step:.3f} ms/step (terms kernel {terms_ms:.3f} ms, finish kernel "
+          f"{finish_ms:.3f} ms), {achieved_tflops:.1f} TFLOP/s algorithmic in the terms kernel",
+          file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)    # 512 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # plain FP64 path (multi-pass), same workload
     fp64 = None
@@ -196,8 +239,10 @@ def main():
                    "R": plan.info.R, "dt_over_tau": DT_OVER_TAU, "terms_per_cell": plan.info.J},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
-                     "traffic": None, "kernel": "k_fused<32>", "avg_launch_ms": round(avg_launch_ms, 4),
-                     "flops_per_cell": plan.info.flops_per_cell},
+                     "traffic": _traffic_per_launch(), "kernel": "k_terms<32>",
+                     "avg_launch_ms": round(terms_ms, 4), "finish_kernel_ms": round(finish_ms, 4),
+                     "call_ms": round(avg_call_ms, 4), "flops_per_cell": plan.info.flops_per_cell,
+                     "source_hash": _fused_source_hash()},
         "cpu_baseline": cpu,
         "fp64_path": fp64,
         "parity": parity,

@@ -194,6 +194,18 @@ fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_spac
                                int32_t n, double T, double dt, double* offsets,
                                const double* bc_f, void* hip_stream);
 
+/*
+ * Per-kernel timing of fks_collide_batch, for measurement tools.  While
+ * enabled, the library records HIP events on the call's stream around each
+ * kernel of the fused path (terms kernel, then finish kernel).
+ * fks_profile_last waits for the last recorded call to finish and writes up
+ * to `capacity` durations in milliseconds (host array), in launch order;
+ * *count receives how many kernels the last call timed (0 if none).
+ * Calls must not overlap while profiling is enabled.
+ */
+fks_status fks_profile_enable(int32_t enable);
+fks_status fks_profile_last(double* kernel_ms, int32_t capacity, int32_t* count);
+
 /* Static string for a status code. */
 const char* fks_status_string(fks_status status);
 

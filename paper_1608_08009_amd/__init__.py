@@ -35,7 +35,7 @@ EXPORTED = [
     "fks_plan_create", "fks_plan_destroy", "fks_plan_query", "fks_plan_copy_tables",
     "fks_workspace_size", "fks_collide_batch", "fks_moments", "fks_conserve",
     "fks_transport_shift", "fks_status_string", "fks_desc_validate",
-    "fks_host_sphere_rule", "fks_host_radial_terms",
+    "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
 ]
 
 
@@ -96,6 +96,8 @@ def lib() -> C.CDLL:
     L.fks_desc_validate.argtypes = [C.POINTER(PlanDesc)]
     L.fks_host_sphere_rule.argtypes = [i32, i32, i32, vp]
     L.fks_host_radial_terms.argtypes = [dbl, dbl, i32, dbl, i32, C.POINTER(i32), vp, vp]
+    L.fks_profile_enable.argtypes = [i32]
+    L.fks_profile_last.argtypes = [vp, i32, C.POINTER(i32)]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -299,6 +301,19 @@ def transport_shift(f_in, f_out, nx: int, ny: int, nz: int, dx: float, bc, n: in
     _check(lib().fks_transport_shift(C.c_void_p(_ptr(f_in)), C.c_void_p(_ptr(f_out)), C.byref(sp), n, T, dt,
                                      C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(bc_f)),
                                      C.c_void_p(_stream_ptr(stream))), "fks_transport_shift")
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().fks_profile_enable(1 if on else 0), "fks_profile_enable")
+
+
+def profile_last() -> list:
+    """Durations (ms) of the kernels of the last fks_collide_batch call (fused path)."""
+    import numpy as np
+    out = np.zeros(8, dtype=np.float64)
+    cnt = C.c_int32()
+    _check(lib().fks_profile_last(out.ctypes.data, 8, C.byref(cnt)), "fks_profile_last")
+    return [float(x) for x in out[:cnt.value]]
 
 
 def host_sphere_rule(n_polar: int, n_azim: int, rule: int = RULE_GAUSS):

@@ -268,6 +268,19 @@ const char* fks_status_string(fks_status s) {
 
 fks_status fks_desc_validate(const fks_plan_desc* desc) { return resolve_desc(desc, nullptr); }
 
+fks_status fks_profile_enable(int32_t enable) {
+    profile_enable(enable != 0);
+    return FKS_OK;
+}
+
+fks_status fks_profile_last(double* kernel_ms, int32_t capacity, int32_t* count) {
+    if (!count || capacity < 0 || (capacity > 0 && !kernel_ms)) return FKS_ERR_INVALID;
+    int c = 0;
+    if (profile_last(kernel_ms, capacity, &c) != hipSuccess) return FKS_ERR_DEVICE;
+    *count = c;
+    return FKS_OK;
+}
+
 fks_status fks_host_sphere_rule(int32_t n_polar, int32_t n_azim, int32_t rule, double* e_w) {
     if (!e_w || n_polar < 1 || n_azim < 1 || n_polar > 256 || n_azim > 256) return FKS_ERR_INVALID;
     if (rule != FKS_RULE_GAUSS && rule != FKS_RULE_MIDPOINT) return FKS_ERR_INVALID;

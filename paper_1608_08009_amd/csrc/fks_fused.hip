@@ -372,6 +372,34 @@ inline int npairs_for(const fks_plan* p, int64_t ncell) {
     return (int)std::max<int64_t>(8, ((want + 7) / 8) * 8 > maxp ? (maxp / 8) * 8 : ((want + 7) / 8) * 8);
 }
 
+// event timing (off by default): events 0..2 bracket k_terms and k_finish
+struct Prof {
+    bool on = false;
+    bool made = false;
+    int device = -1;
+    int count = 0;
+    hipEvent_t ev[3];
+};
+Prof g_prof;
+
+hipError_t prof_mark(int i, hipStream_t st) {
+    if (!g_prof.on) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (!g_prof.made || g_prof.device != dev) {
+        if (g_prof.made)
+            for (auto& x : g_prof.ev) (void)hipEventDestroy(x);
+        g_prof.made = false;
+        for (auto& x : g_prof.ev)
+            if ((e = hipEventCreate(&x)) != hipSuccess) return e;
+        g_prof.made = true;
+        g_prof.device = dev;
+    }
+    g_prof.count = i;
+    return hipEventRecord(g_prof.ev[i], st);
+}
+
 template <int N>
 hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
     constexpr int NT = N * N / Cfg<N>::P;
@@ -389,14 +417,37 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     a.fh = reinterpret_cast<cx<float>*>(base + w.fh);
     a.part = reinterpret_cast<float*>(base + w.part);
     a.gc = p->d_gc;
-    k_terms<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
-    hipError_t e = hipGetLastError();
+    hipError_t e = prof_mark(0, st);
     if (e != hipSuccess) return e;
+    k_terms<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = prof_mark(1, st)) != hipSuccess) return e;
     k_finish<N><<<(unsigned)s.ncell, finish_threads<N>(), 0, st>>>(a);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return prof_mark(2, st);
 }
 
 }  // namespace
+
+void profile_enable(bool on) {
+    g_prof.on = on;
+    g_prof.count = 0;
+}
+
+hipError_t profile_last(double* ms, int cap, int* count) {
+    *count = 0;
+    if (!g_prof.made || g_prof.count < 2) return hipSuccess;
+    hipError_t e = hipEventSynchronize(g_prof.ev[2]);
+    if (e != hipSuccess) return e;
+    int n = 0;
+    for (int i = 0; i < 2 && n < cap; ++i) {
+        float t = 0.0f;
+        if ((e = hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1])) != hipSuccess) return e;
+        ms[n++] = t;
+    }
+    *count = n;
+    return hipSuccess;
+}
 
 bool fused_available(int n) { return n == 8 || n == 16 || n == 32; }
 

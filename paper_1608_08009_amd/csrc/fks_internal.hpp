@@ -62,6 +62,10 @@ size_t generic_workspace_bytes(const fks_plan* plan, int64_t ncell);
 hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
                            hipStream_t stream);
 
+// optional event timing of the fused path (fks_fused.hip)
+void profile_enable(bool on);
+hipError_t profile_last(double* ms, int cap, int* count);
+
 // fused single-kernel FP32 path (fks_fused.hip)
 bool fused_available(int n);
 int fused_grid_size(int n, int device);
