@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=64, help="cells timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=512, help="cells timed on the CPU oracle (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 512 MiB device copy (reference kernel for HBM counters)")

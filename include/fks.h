@@ -125,6 +125,8 @@ fks_status fks_plan_copy_tables(const fks_plan* plan, double* ab_host, double* d
  *   f_out  device, [ncell][n^3] FP64, or NULL: receives f* + dt_over_tau * Q_c
  *          (eq. f_coll).  May alias f (in-place update); must not overlap q_out.
  *   At least one of q_out, f_out must be non-NULL.  ncell >= 0 (0 = nothing).
+ *   f, q_out and f_out must be 16-byte aligned (every cell boundary of an
+ *   array from hipMalloc is).
  */
 typedef struct {
     const fks_plan* plan;
@@ -142,10 +144,11 @@ fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* byt
  * Evaluates Q(f,f) for every cell of every segment (fast spectral form with
  * Nyquist planes zeroed), projects it onto the kernel of the collision
  * invariants in FP64 and writes q_out / f_out.  workspace: device memory of at
- * least fks_workspace_size bytes, owned by the caller, not used concurrently
- * by another call.  No device allocation happens inside.
- * Errors: FKS_ERR_INVALID (NULL plan/f, both outputs NULL, ncell < 0, small
- * workspace), FKS_ERR_DEVICE (launch failure).
+ * least fks_workspace_size bytes, 256-byte aligned, owned by the caller, not
+ * used concurrently by another call.  No device allocation happens inside.
+ * Errors: FKS_ERR_INVALID (NULL plan/f, both outputs NULL, ncell < 0,
+ * misaligned arrays, small or misaligned workspace), FKS_ERR_DEVICE (launch
+ * failure).
  */
 fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace,
                              size_t ws_bytes, void* hip_stream);

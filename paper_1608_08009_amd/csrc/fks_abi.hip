@@ -408,6 +408,8 @@ static fks_status check_segment(const fks_segment& s) {
     if (s.ncell == 0) return FKS_OK;
     if (!s.f || (!s.q_out && !s.f_out)) return FKS_ERR_INVALID;
     if (!std::isfinite(s.dt_over_tau)) return FKS_ERR_INVALID;
+    // the kernels move f, q_out and f_out in 16-byte vectors
+    if (((uintptr_t)s.f | (uintptr_t)s.q_out | (uintptr_t)s.f_out) & 15u) return FKS_ERR_INVALID;
     size_t bytes = (size_t)s.ncell * s.plan->desc.n * s.plan->desc.n * s.plan->desc.n * sizeof(double);
     if (s.q_out && s.f_out) {
         const char* a = (const char*)s.q_out;
@@ -453,7 +455,7 @@ fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* worksp
         if (st != FKS_OK) return st;
         need = std::max(need, segment_ws(segs[i]));
     }
-    if (need > 0 && (!workspace || ws_bytes < need)) return FKS_ERR_INVALID;
+    if (need > 0 && (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255u))) return FKS_ERR_INVALID;
     hipStream_t s = (hipStream_t)hip_stream;
     for (int i = 0; i < nseg; ++i) {
         const fks_segment& g = segs[i];

@@ -26,8 +26,20 @@
 //   B: pencil (kx = kx_p, z = lo), registers over y
 //   A: pencil (kx_p, ky_p), registers over kz                 (spectral side)
 // With P = 2 a thread owns the mirrored pencils (kx, ky) and (-kx, -ky), so the
-// tables and fhat (even and Hermitian in k) are loaded once per term for both;
-// for hi = 0 the second pencil is the Nyquist pencil kx = n/2, which is zero.
+// tables and fhat (even and Hermitian in k) are loaded once per term for both.
+// For hi = 0 the second pencil stands for the Nyquist pencil kx = n/2, which
+// is zero: its A and B stages run on a duplicate of another pencil and its
+// B -> C writes go to the unread padding column, so LDS row kx = n/2 keeps the
+// zeros that the A -> B exchange left there (row ky = n/2 of every group is
+// the zero Nyquist plane ky = n/2).
+//
+// Register budget (n = 32): a thread holds 2 x 32 complex values in flight and
+// 64 accumulators; the scheduling fences keep the compiler from interleaving
+// the per-pencil transforms, which would otherwise push the live set past 256
+// VGPRs and spill the accumulators every term.  The own-pencil table and
+// spectrum values of term j+1 are loaded during the last x transform of term j
+// (software pipelining); the mirror-pencil values are loaded at the start of
+// the term.
 // LDS holds HP blocks of n rows with row stride n+1 (padding against bank
 // conflicts; every LDS access is a per-thread base plus an immediate offset).
 // A <-> B only swaps (lane, register) inside the n threads sharing hi: it goes
@@ -199,16 +211,31 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             constexpr int p = decltype(pI)::value;
             sfor<N>([&](auto xI) { q[p][decltype(xI)::value] = 0.0f; });
         });
+        // table and spectrum at the own pencil (hi, lo), kz in [0, n/2): loaded one
+        // term ahead, during the last x transform of the previous term
+        cx<float> pt[N / 2], pf[N / 2];
+        auto load_own = [&](int jj) {
+            const char* tj = (const char*)(A.tab + (size_t)jj * H);
+            const uint32_t oa8 = uint32_t(opaque(hi * N + lo)) * 8u;
+            sfor<N / 2>([&](auto kI) {
+                constexpr int kz = decltype(kI)::value;
+                constexpr uint32_t zo = kz * NN * sizeof(cx<float>);
+                pt[kz] = *(const cx<float>*)(tj + (oa8 + zo));
+                pf[kz] = *(const cx<float>*)((const char*)fh + (oa8 + zo));
+            });
+        };
+        load_own(min(j_begin, A.J - 1));
         for (int j = j_begin; j < j_end; ++j) {
             const cx<float>* tj = A.tab + (size_t)j * H;
             cx<float> za[P][N];
-            // positions: own pencil (hi, lo) and its mirror (-hi, -lo); kz in [0, n/2)
-            const int oa = opaque(hi * N + lo);
+            // mirror pencil (-hi, -lo), kz in [0, n/2)
             const int ob = opaque(((N - hi) & (N - 1)) * N + ((N - lo) & (N - 1)));
             sfor<N / 2>([&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
-                const cx<float> ta = tj[oa + kz * NN], fa = fh[oa + kz * NN];
-                const cx<float> tb = tj[ob + kz * NN], fb = fh[ob + kz * NN];
+                constexpr uint32_t zo = kz * NN * sizeof(cx<float>);
+                const cx<float> ta = pt[kz], fa = pf[kz];
+                const cx<float> tb = *(const cx<float>*)((const char*)tj + (uint32_t(ob) * 8u + zo));
+                const cx<float> fb = *(const cx<float>*)((const char*)fh + (uint32_t(ob) * 8u + zo));
                 // pencil 0 = (hi, lo): kz from (hi, lo); -kz from the mirror (conjugated)
                 za[0][kz] = cmulf(ta, fa);
                 if constexpr (kz > 0) za[0][N - kz] = cmulf_conj(tb, fb);
@@ -221,14 +248,13 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             za[0][N / 2] = cx<float>{0.0f, 0.0f};
             if constexpr (P == 2) {
                 za[1][N / 2] = cx<float>{0.0f, 0.0f};
-                if (hi == 0) {   // second pencil of hi = 0 is the (zero) Nyquist pencil kx = n/2
-                    sfor<N>([&](auto kI) { za[1][decltype(kI)::value] = cx<float>{0.0f, 0.0f}; });
-                }
             }
             cx<float> zb[P][N];
             sfor<P>([&](auto pI) {   // z transform, then A -> B inside the group
                 constexpr int p = decltype(pI)::value;
+                __builtin_amdgcn_sched_barrier(0);
                 fft<float, N, 1>(za[p]);
+                __builtin_amdgcn_sched_barrier(0);
                 cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // row = this pencil's actual ky
                 sfor<N>([&](auto zI) {
                     constexpr int z = decltype(zI)::value;
@@ -248,7 +274,9 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
                 __syncthreads();
                 sfor<P>([&](auto pI) {
                     constexpr int p = decltype(pI)::value;
-                    cx<float>* dst = lds + kx_of<N, P>(p, hi) * RS + lo;   // row kx, column z
+                    // row kx, column z; the second pencil of hi = 0 (kx = n/2) goes to the
+                    // unread padding column, so row n/2 keeps the zeros of the A -> B exchange
+                    cx<float>* dst = lds + ((P == 2 && p == 1 && hi == 0) ? lo * RS + N : kx_of<N, P>(p, hi) * RS + lo);
                     sfor<HP>([&](auto yI) {
                         constexpr int yy = decltype(yI)::value;
                         dst[yy * BS] = zb[p][HP * r + yy];
@@ -262,6 +290,11 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             });
             sfor<P>([&](auto pI) {
                 constexpr int p = decltype(pI)::value;
+                if constexpr (p == P - 1) {   // next term's own-pencil loads overlap this transform
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_own(min(j + 1, j_end - 1));
+                }
+                __builtin_amdgcn_sched_barrier(0);
                 fft<float, N, 1>(zc[p]);
                 sfor<N>([&](auto xI) {
                     constexpr int x = decltype(xI)::value;
@@ -285,57 +318,82 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
 
 // Sum of the two partials, FP64 projection onto the kernel of the collision
 // invariants and the update; one workgroup per cell, values kept in registers.
-// With FT = min(1024, n^3) threads, thread t owns the nodes t + FT k: its (y, z)
-// are fixed and x advances by FT / n^2 per step.
+// Thread t owns VW = 4 consecutive nodes in z starting at node 4 t + 4 FT k
+// (16-byte partial loads, 32-byte f loads and stores): its (y, z) are fixed
+// and x advances by 4 FT / n^2 per step.
 template <int N>
-constexpr int finish_threads() { return N * N * N < 1024 ? N * N * N : 1024; }
+constexpr int finish_threads() { return N * N * N / 4 < 512 ? N * N * N / 4 : 512; }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
 template <int N>
 __global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
     constexpr int N3 = N * N * N;
+    constexpr int VW = 4;
     constexpr int FT = finish_threads<N>();
-    constexpr int V = N3 / FT;
-    constexpr int XS = FT / (N * N);   // x advance per step
+    constexpr int V = N3 / (FT * VW);        // vectors per thread
+    constexpr int XS = FT * VW / (N * N);    // x advance per step
+    static_assert(V * FT * VW == N3 && XS * N * N == FT * VW, "finish layout");
     __shared__ double red[5 * (FT / 64)];
     const int t = threadIdx.x;
     const int64_t cell = blockIdx.x;
     const float* p0 = A.part + cell * 2 * (int64_t)N3;
     const float* p1 = p0 + N3;
     const double h = A.gc->dv / A.gc->T;
-    const int z = t % N, y = (t / N) % N, x0 = t / (N * N);
-    const double uy = -1.0 + y * h, uz = -1.0 + z * h, r2 = uy * uy + uz * uz;
-    double qv[V];
+    const int z0 = (VW * t) % N, y = (VW * t / N) % N, x0 = VW * t / (N * N);
+    const double uy = -1.0 + y * h;
+    double uz[VW];
+#pragma unroll
+    for (int c = 0; c < VW; ++c) uz[c] = -1.0 + (z0 + c) * h;
+    double qv[V][VW];
     double m[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-        const int i = t + k * FT;
+        const int i = VW * t + k * FT * VW;
         const double ux = -1.0 + (x0 + k * XS) * h;
-        qv[k] = (double)__builtin_nontemporal_load(p0 + i) + (double)__builtin_nontemporal_load(p1 + i);
-        m[0] += qv[k];
-        m[1] = fma(qv[k], ux, m[1]);
-        m[2] = fma(qv[k], uy, m[2]);
-        m[3] = fma(qv[k], uz, m[3]);
-        m[4] = fma(qv[k], fma(ux, ux, r2), m[4]);
+        const f4v a = __builtin_nontemporal_load((const f4v*)(p0 + i));
+        const f4v b = __builtin_nontemporal_load((const f4v*)(p1 + i));
+        const double rxy = fma(ux, ux, uy * uy);
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const double q = (double)a[c] + (double)b[c];
+            qv[k][c] = q;
+            m[0] += q;
+            m[1] = fma(q, ux, m[1]);
+            m[2] = fma(q, uy, m[2]);
+            m[3] = fma(q, uz[c], m[3]);
+            m[4] = fma(q, fma(uz[c], uz[c], rxy), m[4]);
+        }
     }
     block_sum5<FT>(m, red);
     double lam[5];
     solve5(*A.gc, m, lam);
-    const double l0 = lam[0] + lam[2] * uy + lam[3] * uz + lam[4] * r2;
-    const int64_t base = cell * (int64_t)N3 + t;
+    const int64_t base = cell * (int64_t)N3 + VW * t;
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         const double ux = -1.0 + (x0 + k * XS) * h;
-        qv[k] -= fma(lam[4], ux * ux, fma(lam[1], ux, l0));
+        const double lx = fma(lam[4], fma(ux, ux, uy * uy), fma(lam[1], ux, fma(lam[2], uy, lam[0])));
+#pragma unroll
+        for (int c = 0; c < VW; ++c) qv[k][c] -= fma(lam[4], uz[c] * uz[c], fma(lam[3], uz[c], lx));
     }
     if (A.q_out) {
 #pragma unroll
-        for (int k = 0; k < V; ++k) __builtin_nontemporal_store(qv[k], A.q_out + base + k * FT);
+        for (int k = 0; k < V; ++k) {
+            d2v* o = (d2v*)(A.q_out + base + k * FT * VW);
+            __builtin_nontemporal_store(d2v{qv[k][0], qv[k][1]}, o);
+            __builtin_nontemporal_store(d2v{qv[k][2], qv[k][3]}, o + 1);
+        }
     }
     if (A.f_out) {
 #pragma unroll
-        for (int k = 0; k < V; ++k)
-            __builtin_nontemporal_store(fma(A.dt, qv[k], __builtin_nontemporal_load(A.f + base + k * FT)),
-                                        A.f_out + base + k * FT);
+        for (int k = 0; k < V; ++k) {
+            const d2v* fi = (const d2v*)(A.f + base + k * FT * VW);
+            d2v* o = (d2v*)(A.f_out + base + k * FT * VW);
+            const d2v f0 = __builtin_nontemporal_load(fi), f1 = __builtin_nontemporal_load(fi + 1);
+            __builtin_nontemporal_store(d2v{fma(A.dt, qv[k][0], f0[0]), fma(A.dt, qv[k][1], f0[1])}, o);
+            __builtin_nontemporal_store(d2v{fma(A.dt, qv[k][2], f1[0]), fma(A.dt, qv[k][3], f1[1])}, o + 1);
+        }
     }
 }
 

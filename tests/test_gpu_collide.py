@@ -222,6 +222,20 @@ def test_empty_batch_and_invalid_arguments():
     small = torch.empty(max(need - 1, 1), dtype=torch.uint8, device="cuda")
     with pytest.raises(fks.FksError):
         fks.collide_batch(seg, workspace=small)
+    # arrays must be 16-byte aligned, the workspace 256-byte aligned
+    flat = torch.zeros(2 * 512 + 1, dtype=torch.float64, device="cuda")
+    odd = flat[1:].view(2, 8, 8, 8)
+    with pytest.raises(fks.FksError) as e:
+        fks.collide_batch([(plan, odd, q, None, 2, 0.0)])
+    assert e.value.status == fks.FKS_ERR_INVALID
+    with pytest.raises(fks.FksError) as e:
+        fks.collide_batch([(plan, g, odd, None, 2, 0.0)])
+    assert e.value.status == fks.FKS_ERR_INVALID
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(fks.FksError) as e:
+        fks.collide_batch(seg, workspace=ws[16:])
+    assert e.value.status == fks.FKS_ERR_INVALID
+    fks.collide_batch(seg, workspace=ws[256:])
     with pytest.raises(fks.FksError) as e:
         fks.Plan(fks.Desc(n=10, T=8.0))
     assert e.value.status == fks.FKS_ERR_UNSUPPORTED
