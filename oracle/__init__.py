@@ -11,3 +11,4 @@ Parity status of each function is stated in its docstring; the pins live in
 ``tests/test_oracle_pins.py``.
 """
 from .fks_oracle import *  # noqa: F401,F403
+from . import fks_oracle2d  # noqa: F401  (two-dimensional Maxwell molecules)
