@@ -73,7 +73,21 @@ typedef struct {
     double  radial_tol;   /* <= 0 -> 1e-4 */
     int32_t precision;    /* fks_precision */
     uint32_t flags;       /* FKS_FLAG_* */
+    int32_t dim;          /* velocity dimension d_v: 3 (0 -> 3) or 2 (see below) */
 } fks_plan_desc;
+
+/*
+ * dim = 2: Maxwell molecules in two velocity dimensions, the decoupled
+ * two-dimensional formula of Section 3.3 (eq. dfor0): B_F(l, m) =
+ * 2 C_0 (pi/A) sum_p phi(kappa l.e_p) phi(kappa m.e_p^perp), phi(s) = 2R Sinc(Rs),
+ * e_p = (cos t_p, sin t_p), t_p = pi p / A, p = 1..A.  Fields: n in
+ * {8, 12, 16, 24, 32, 48, 64} (FP64: n <= 32); n_polar = A (angles);
+ * n_azim must be 1; gamma must be 0 (FKS_ERR_UNSUPPORTED otherwise);
+ * c_gamma = C_0, <= 0 -> 1/(2 pi) (then the loss term is rho f);
+ * radial_terms 0 or 1; rule and radial_tol are ignored; FKS_FLAG_FORCE_GENERIC
+ * is unsupported.  Arrays are [ncell][n][n] FP64 (x-major), the invariants are
+ * (1, v_x, v_y, |v|^2), and fks_collide_batch needs no workspace for them.
+ */
 
 typedef struct fks_plan fks_plan;   /* opaque: immutable after creation, owns device tables */
 
@@ -88,6 +102,7 @@ typedef struct {
     int32_t fused;             /* 1 if fks_collide_batch uses the single fused kernel */
     size_t  table_bytes;       /* device bytes held by the plan */
     double  flops_per_cell;    /* algorithmic flop count of one Q evaluation (see design notes) */
+    int32_t dim;               /* velocity dimension (2 or 3) */
 } fks_plan_info;
 
 /*
@@ -114,6 +129,9 @@ fks_status fks_plan_query(const fks_plan* plan, fks_plan_info* info);
  * k = (kx, ky, kz) in FFT storage order, kz in [0, n/2]; the last term
  * (j = J-1) is the loss term (-L(k), 1).  Either pointer may be NULL.
  * dirs_host: [M][4] doubles = (e_x, e_y, e_z, w_e).  Synchronous.
+ * dim = 2: ab_host is [J][n][n][2] = (sqrt(w) alpha_p(k), sqrt(w) alpha'_p(k)),
+ * w = 2 C_0 pi / A, k = (kx, ky) in FFT storage order, and the loss term is
+ * (-L(k)/s, s) with s = sqrt(L(0)); dirs_host rows are (cos t_p, sin t_p, 0, pi/A).
  */
 fks_status fks_plan_copy_tables(const fks_plan* plan, double* ab_host, double* dirs_host);
 
@@ -220,11 +238,15 @@ const char* fks_status_string(fks_status status);
  *     e_w [n_polar*n_azim][4] = (e_x, e_y, e_z, w).
  *   fks_host_radial_terms: radial expansion for gamma (K requested, 0 -> by tol);
  *     *K_out receives K; nodes [nq], coef [nq][K] (row-major) may be NULL to query K.
+ *   fks_host_tables_2d: the FP64 tables a dim = 2 plan uploads, ab [J][n][n][2]
+ *     laid out as fks_plan_copy_tables describes; *J_out receives J = A + 1 and
+ *     ab may be NULL to query it.
  */
 fks_status fks_desc_validate(const fks_plan_desc* desc);
 fks_status fks_host_sphere_rule(int32_t n_polar, int32_t n_azim, int32_t rule, double* e_w);
 fks_status fks_host_radial_terms(double gamma, double R, int32_t K, double tol, int32_t nq,
                                  int32_t* K_out, double* nodes, double* coef);
+fks_status fks_host_tables_2d(const fks_plan_desc* desc, int32_t* J_out, double* ab);
 
 #ifdef __cplusplus
 }

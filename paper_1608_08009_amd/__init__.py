@@ -36,6 +36,7 @@ EXPORTED = [
     "fks_workspace_size", "fks_collide_batch", "fks_moments", "fks_conserve",
     "fks_transport_shift", "fks_status_string", "fks_desc_validate",
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
+    "fks_host_tables_2d",
 ]
 
 
@@ -44,7 +45,7 @@ class PlanDesc(C.Structure):
         ("n", C.c_int32), ("T", C.c_double), ("R", C.c_double), ("gamma", C.c_double),
         ("c_gamma", C.c_double), ("n_polar", C.c_int32), ("n_azim", C.c_int32),
         ("rule", C.c_int32), ("radial_terms", C.c_int32), ("radial_tol", C.c_double),
-        ("precision", C.c_int32), ("flags", C.c_uint32),
+        ("precision", C.c_int32), ("flags", C.c_uint32), ("dim", C.c_int32),
     ]
 
 
@@ -53,6 +54,7 @@ class PlanInfo(C.Structure):
         ("n", C.c_int32), ("M", C.c_int32), ("K", C.c_int32), ("J", C.c_int32),
         ("R", C.c_double), ("c_gamma", C.c_double), ("precision", C.c_int32),
         ("fused", C.c_int32), ("table_bytes", C.c_size_t), ("flops_per_cell", C.c_double),
+        ("dim", C.c_int32),
     ]
 
 
@@ -98,6 +100,7 @@ def lib() -> C.CDLL:
     L.fks_host_radial_terms.argtypes = [dbl, dbl, i32, dbl, i32, C.POINTER(i32), vp, vp]
     L.fks_profile_enable.argtypes = [i32]
     L.fks_profile_last.argtypes = [vp, i32, C.POINTER(i32)]
+    L.fks_host_tables_2d.argtypes = [C.POINTER(PlanDesc), C.POINTER(i32), vp]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -155,10 +158,18 @@ class Desc:
     radial_tol: float = 0.0
     precision: int = PREC_F32_FIX64
     flags: int = 0
+    dim: int = 3
 
     def c(self) -> PlanDesc:
         return PlanDesc(self.n, self.T, self.R, self.gamma, self.c_gamma, self.n_polar, self.n_azim,
-                        self.rule, self.radial_terms, self.radial_tol, self.precision, self.flags)
+                        self.rule, self.radial_terms, self.radial_tol, self.precision, self.flags,
+                        self.dim)
+
+
+def desc2d(n: int, T: float, A: int = 8, precision: int = PREC_F32_FIX64, R: float = 0.0,
+           c0: float = 0.0) -> Desc:
+    """Two-dimensional Maxwell molecules with A angles (fks_plan_desc with dim = 2)."""
+    return Desc(n=n, T=T, gamma=0.0, R=R, c_gamma=c0, n_polar=A, n_azim=1, precision=precision, dim=2)
 
 
 def desc_validate(d: Desc) -> int:
@@ -190,6 +201,15 @@ class Plan:
     def n(self) -> int:
         return self.info.n
 
+    @property
+    def dim(self) -> int:
+        return self.info.dim
+
+    @property
+    def cell_size(self) -> int:
+        """Velocity nodes per cell: n^dim."""
+        return self.info.n ** self.info.dim
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             lib().fks_plan_destroy(self._h)
@@ -208,10 +228,12 @@ class Plan:
             pass
 
     def tables(self):
-        """(ab [J, n/2+1, n, n, 2] FP64 numpy, dirs [M, 4]) copied from the device."""
+        """(ab FP64 numpy, dirs [M, 4]) copied from the device; ab is [J, n/2+1, n, n, 2]
+        for dim = 3 and [J, n, n, 2] for dim = 2."""
         import numpy as np
         n, J, M = self.info.n, self.info.J, self.info.M
-        ab = np.empty((J, n // 2 + 1, n, n, 2), dtype=np.float64)
+        shape = (J, n, n, 2) if self.info.dim == 2 else (J, n // 2 + 1, n, n, 2)
+        ab = np.empty(shape, dtype=np.float64)
         dirs = np.empty((M, 4), dtype=np.float64)
         _check(lib().fks_plan_copy_tables(self.handle, ab.ctypes.data, dirs.ctypes.data),
                "fks_plan_copy_tables")
@@ -243,7 +265,7 @@ def collide_batch(segments, workspace=None, stream=None):
     """
     import torch
     for (plan, f, q_out, f_out, ncell, dt) in segments:
-        nn = ncell * plan.n ** 3
+        nn = ncell * plan.cell_size
         _require_device_f64(f, "f", nn)
         _require_device_f64(q_out, "q_out", nn)
         _require_device_f64(f_out, "f_out", nn)
@@ -257,8 +279,9 @@ def collide_batch(segments, workspace=None, stream=None):
 
 
 def collide(plan: Plan, f, q_out=None, f_out=None, dt_over_tau: float = 0.0, workspace=None, stream=None):
-    """Single-segment convenience wrapper; f is [ncell, n, n, n] float64 on the GPU."""
-    ncell = f.shape[0] if f.dim() == 4 else 1
+    """Single-segment convenience wrapper; f is [ncell, n, n, n] (dim 3) or [ncell, n, n]
+    (dim 2) float64 on the GPU."""
+    ncell = f.numel() // plan.cell_size
     return collide_batch([(plan, f, q_out, f_out, ncell, dt_over_tau)], workspace, stream)
 
 
@@ -321,6 +344,17 @@ def host_sphere_rule(n_polar: int, n_azim: int, rule: int = RULE_GAUSS):
     out = np.empty((n_polar * n_azim, 4), dtype=np.float64)
     _check(lib().fks_host_sphere_rule(n_polar, n_azim, rule, out.ctypes.data), "fks_host_sphere_rule")
     return out
+
+
+def host_tables_2d(d: Desc):
+    """FP64 tables a dim = 2 plan uploads: [J, n, n, 2] (host computation, no GPU)."""
+    import numpy as np
+    cd = d.c()
+    J = C.c_int32()
+    _check(lib().fks_host_tables_2d(C.byref(cd), C.byref(J), None), "fks_host_tables_2d")
+    ab = np.empty((J.value, d.n, d.n, 2), dtype=np.float64)
+    _check(lib().fks_host_tables_2d(C.byref(cd), C.byref(J), ab.ctypes.data), "fks_host_tables_2d")
+    return ab
 
 
 def host_radial_terms(gamma: float, R: float, K: int = 0, tol: float = 1e-4, nq: int = 200):

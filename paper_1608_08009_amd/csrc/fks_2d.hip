@@ -1,0 +1,288 @@
+// Two velocity dimensions: the fast spectral operator for Maxwell molecules
+// (Section 3.3, decoupled two-dimensional formula, eq. dfor0), one kernel per
+// segment, FP64 or FP32 transforms with the FP64 conservation fix.
+//
+//   B_F(l, m) = w sum_p alpha_p(l) alpha'_p(m),  alpha_p(k) = phi(kappa k.e_p),
+//   alpha'_p(k) = phi(kappa k.e_p^perp), phi(s) = 2R Sinc(Rs), t_p = pi p / A,
+//   w = 2 C_0 pi / A.
+//
+// Per cell: fhat = n^-2 FFT(f) with the Nyquist lines zeroed; for each term
+// (A gain terms, then the loss term) z = F^{-1}[(a + i b) fhat] and
+// Q += Re z Im z, where (a, b) = (sqrt(w) alpha_p, sqrt(w) alpha'_p) for a gain
+// term and (-L/s, s), s = sqrt(L(0)), for the loss term (Im z is then s f_N).
+// Then the FP64 projection onto the kernel of (1, v_x, v_y, |v|^2)
+// (eq. minim1) and the update f + dt/tau Q_c (eq. f_coll).
+//
+// Layout: n threads per cell, CPB cells per workgroup.  Thread i holds row
+// x = i of the cell in the physical layout (registers over y) and column
+// ky = i in the spectral layout (registers over kx); one LDS block of n rows
+// (stride n+1) per cell turns one layout into the other.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fks_fft.hpp"
+#include "fks_internal.hpp"
+
+namespace fks {
+
+bool supported_n_2d(int n, int precision) {
+    switch (n) {
+        case 8: case 12: case 16: case 24: case 32: return true;
+        case 48: case 64: return precision == FKS_PREC_F32_FIX64;
+        default: return false;
+    }
+}
+
+// Gram matrix of the scaled invariants over the n^2 grid, inverted in long double.
+GridConst2 grid_const2(int n, double T) {
+    GridConst2 g{};
+    g.T = T;
+    g.dv = 2.0 * T / n;
+    long double G[4][4] = {};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            long double vx = (-T + i * g.dv) / T, vy = (-T + j * g.dv) / T;
+            long double ph[4] = {1.0L, vx, vy, vx * vx + vy * vy};
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) G[a][b] += ph[a] * ph[b];
+        }
+    long double M[4][8] = {};
+    for (int a = 0; a < 4; ++a) {
+        for (int b = 0; b < 4; ++b) M[a][b] = G[a][b];
+        M[a][4 + a] = 1.0L;
+    }
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabsl(M[r][c]) > fabsl(M[piv][c])) piv = r;
+        for (int k = 0; k < 8; ++k) std::swap(M[c][k], M[piv][k]);
+        long double d = M[c][c];
+        for (int k = 0; k < 8; ++k) M[c][k] /= d;
+        for (int r = 0; r < 4; ++r)
+            if (r != c) {
+                long double m = M[r][c];
+                for (int k = 0; k < 8; ++k) M[r][k] -= m * M[c][k];
+            }
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) g.ginv[a * 4 + b] = (double)M[a][4 + b];
+    return g;
+}
+
+// Host FP64 tables of a dim = 2 plan, [J][n][n][2], k in FFT storage order.
+void tables_2d(const fks_plan_desc& d, std::vector<double>& ab) {
+    const int n = d.n, A = d.n_polar, J = A + 1;
+    const double pi = 3.14159265358979323846;
+    const double kappa = pi / d.T, R = d.R;
+    const double w = 2.0 * d.c_gamma * pi / A, sw = std::sqrt(w);
+    auto phi = [R](double s) {   // 2R Sinc(Rs)
+        double x = R * s;
+        return std::fabs(x) < 1e-8 ? 2.0 * R * (1.0 - x * x / 6.0) : 2.0 * R * std::sin(x) / x;
+    };
+    auto kw = [n](int i) { return i < n / 2 ? i : i - n; };
+    ab.assign((size_t)J * n * n * 2, 0.0);
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int p = 1; p <= A; ++p) {
+        const double t = pi * p / A, c = std::cos(t), s = std::sin(t);
+        double* o = &ab[(size_t)(p - 1) * n * n * 2];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double kx = kw(i), ky = kw(j);
+                const double a = phi(kappa * (kx * c + ky * s));
+                const double b = phi(kappa * (-kx * s + ky * c));
+                o[((size_t)i * n + j) * 2] = sw * a;
+                o[((size_t)i * n + j) * 2 + 1] = sw * b;
+                L[(size_t)i * n + j] += w * a * b;
+            }
+    }
+    const double sl = std::sqrt(L[0]);
+    double* o = &ab[(size_t)A * n * n * 2];
+    for (size_t k = 0; k < (size_t)n * n; ++k) {
+        o[2 * k] = -L[k] / sl;
+        o[2 * k + 1] = sl;
+    }
+}
+
+namespace {
+
+// cells per workgroup: n threads each, at most 256 threads and 128 KiB of LDS
+template <typename R, int N>
+constexpr int cells_per_block() {
+    constexpr int by_threads = 256 / N;
+    constexpr int by_lds = (128 * 1024) / (N * (N + 1) * (int)sizeof(cx<R>));
+    constexpr int c = by_threads < by_lds ? by_threads : by_lds;
+    return c < 1 ? 1 : c;
+}
+
+struct Args2 {
+    const double* f;
+    double* q_out;
+    double* f_out;
+    int64_t ncell;
+    double dt;
+    const void* tab;   // [J][N][N] pairs (a, b) in the transform type
+    int J;
+    const GridConst2* gc;
+};
+
+template <typename R, int N>
+__global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Args2 A) {
+    constexpr int CPB = cells_per_block<R, N>();
+    constexpr int RS = N + 1;
+    constexpr int NN = N * N;
+    __shared__ cx<R> lds[CPB * N * RS];
+    static_assert(CPB * N * 4 * sizeof(double) <= sizeof(lds), "reduction buffer");
+    const int t = threadIdx.x;
+    const int c = t / N, i = t % N;
+    const int64_t cell = (int64_t)blockIdx.x * CPB + c;
+    const bool live = cell < A.ncell;
+    cx<R>* const blk = lds + c * N * RS;
+    const cx<R>* const tab = (const cx<R>*)A.tab;
+
+    // ---- forward transform: row x = i over y, then columns over x ----
+    cx<R> z[N];
+    {
+        const double* fr = A.f + (live ? cell : 0) * (int64_t)NN + i * N;
+        sfor<N>([&](auto yI) {
+            constexpr int y = decltype(yI)::value;
+            z[y] = cx<R>{live ? (R)fr[y] : R(0), R(0)};
+        });
+    }
+    fft<R, N, -1>(z);
+    sfor<N>([&](auto kI) {   // row layout -> column layout: blk[ky][x]
+        constexpr int k = decltype(kI)::value;
+        blk[k * RS + i] = z[k];
+    });
+    __syncthreads();
+    cx<R> fh[N];   // column ky = i, registers over kx
+    sfor<N>([&](auto kI) {
+        constexpr int k = decltype(kI)::value;
+        fh[k] = blk[i * RS + k];
+    });
+    __syncthreads();
+    fft<R, N, -1>(fh);
+    {
+        const R s = (i == N / 2) ? R(0) : R(1) / R(NN);
+        sfor<N>([&](auto kI) {
+            constexpr int k = decltype(kI)::value;
+            const R sk = (k == N / 2) ? R(0) : s;
+            fh[k] = cx<R>{fh[k].x * sk, fh[k].y * sk};
+        });
+    }
+
+    // ---- terms: z = F^{-1}[(a + i b) fhat], Q += Re z Im z ----
+    R q[N];
+    sfor<N>([&](auto yI) { q[decltype(yI)::value] = R(0); });
+    for (int j = 0; j < A.J; ++j) {
+        const cx<R>* tj = tab + (size_t)j * NN + i;
+        sfor<N>([&](auto kI) {
+            constexpr int k = decltype(kI)::value;
+            const cx<R> ab = tj[k * N];   // (a, b) at (kx = k, ky = i)
+            z[k] = cx<R>{ab.x * fh[k].x - ab.y * fh[k].y, ab.x * fh[k].y + ab.y * fh[k].x};
+        });
+        fft<R, N, 1>(z);   // over kx: column ky = i, registers over x
+        sfor<N>([&](auto xI) {
+            constexpr int x = decltype(xI)::value;
+            blk[x * RS + i] = z[x];
+        });
+        __syncthreads();
+        sfor<N>([&](auto kI) {
+            constexpr int k = decltype(kI)::value;
+            z[k] = blk[i * RS + k];
+        });
+        __syncthreads();
+        fft<R, N, 1>(z);   // over ky: row x = i, registers over y
+        sfor<N>([&](auto yI) {
+            constexpr int y = decltype(yI)::value;
+            q[y] = fma(z[y].x, z[y].y, q[y]);
+        });
+    }
+
+    // ---- FP64 projection onto the kernel of (1, v_x, v_y, |v|^2) ----
+    const GridConst2 g = *A.gc;
+    const double h = g.dv / g.T;
+    const double ux = -1.0 + i * h;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    sfor<N>([&](auto yI) {
+        constexpr int y = decltype(yI)::value;
+        const double uy = -1.0 + y * h, qq = (double)q[y];
+        m[0] += qq;
+        m[1] = fma(qq, ux, m[1]);
+        m[2] = fma(qq, uy, m[2]);
+        m[3] = fma(qq, fma(ux, ux, uy * uy), m[3]);
+    });
+    double* red = (double*)lds;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) red[(c * N + i) * 4 + a] = m[a];
+    __syncthreads();
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) s[a] += red[(c * N + k) * 4 + a];
+    double lam[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v = fma(g.ginv[a * 4 + b], s[b], v);
+        lam[a] = v;
+    }
+    if (!live) return;
+    const int64_t base = cell * (int64_t)NN + i * N;
+    const double lx = fma(lam[1], ux, lam[0]);
+    sfor<N>([&](auto yI) {
+        constexpr int y = decltype(yI)::value;
+        const double uy = -1.0 + y * h;
+        const double qc = (double)q[y] - (lx + lam[2] * uy + lam[3] * fma(ux, ux, uy * uy));
+        if (A.q_out) A.q_out[base + y] = qc;
+        if (A.f_out) A.f_out[base + y] = fma(A.dt, qc, A.f[base + y]);
+    });
+}
+
+template <typename R, int N>
+hipError_t launch2d(const Args2& a, hipStream_t st) {
+    constexpr int CPB = cells_per_block<R, N>();
+    const int64_t blocks = (a.ncell + CPB - 1) / CPB;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    k_collide2d<R, N><<<(unsigned)blocks, CPB * N, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t dispatch2d(int n, const Args2& a, hipStream_t st) {
+    switch (n) {
+        case 8: return launch2d<R, 8>(a, st);
+        case 12: return launch2d<R, 12>(a, st);
+        case 16: return launch2d<R, 16>(a, st);
+        case 24: return launch2d<R, 24>(a, st);
+        case 32: return launch2d<R, 32>(a, st);
+        default: break;
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (n == 48) return launch2d<R, 48>(a, st);
+        if (n == 64) return launch2d<R, 64>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t collide_2d(const fks_plan* p, const fks_segment& s, hipStream_t st) {
+    Args2 a{};
+    a.f = s.f;
+    a.q_out = s.q_out;
+    a.f_out = s.f_out;
+    a.ncell = s.ncell;
+    a.dt = s.dt_over_tau;
+    a.J = p->J;
+    a.gc = p->d_gc2;
+    if (p->desc.precision == FKS_PREC_F64) {
+        a.tab = p->d_tab64;
+        return dispatch2d<double>(p->desc.n, a, st);
+    }
+    a.tab = p->d_tab32;
+    return dispatch2d<float>(p->desc.n, a, st);
+}
+
+}  // namespace fks

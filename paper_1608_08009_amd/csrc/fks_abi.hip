@@ -240,9 +240,20 @@ static fks_status resolve_desc(const fks_plan_desc* in, fks_plan_desc* out) {
     if (d.radial_terms < 0 || d.radial_terms > 200) return FKS_ERR_INVALID;
     if ((d.flags & ~FKS_FLAG_FORCE_GENERIC) != 0) return FKS_ERR_INVALID;
     if (d.n <= 0) return FKS_ERR_INVALID;
-    if (!supported_n(d.n)) return FKS_ERR_UNSUPPORTED;
+    if (d.dim == 0) d.dim = 3;
+    if (d.dim != 2 && d.dim != 3) return FKS_ERR_INVALID;
+    if (d.dim == 2) {
+        // Maxwell molecules in two velocity dimensions (Section 3.3, eq. dfor0)
+        if (d.n_azim != 1 || d.radial_terms > 1) return FKS_ERR_INVALID;
+        if (d.gamma != 0.0 || (d.flags & FKS_FLAG_FORCE_GENERIC)) return FKS_ERR_UNSUPPORTED;
+        if (!supported_n_2d(d.n, d.precision)) return FKS_ERR_UNSUPPORTED;
+        if (d.c_gamma <= 0) d.c_gamma = 1.0 / (2.0 * kPi);
+        d.radial_terms = 1;
+    } else {
+        if (!supported_n(d.n)) return FKS_ERR_UNSUPPORTED;
+        if (d.c_gamma <= 0) d.c_gamma = 1.0 / (4.0 * kPi);
+    }
     if (d.R <= 0) d.R = 2.0 * d.T / (3.0 + std::sqrt(2.0));
-    if (d.c_gamma <= 0) d.c_gamma = 1.0 / (4.0 * kPi);
     if (d.radial_tol <= 0) d.radial_tol = 1e-4;
     if (out) *out = d;
     return FKS_OK;
@@ -302,6 +313,69 @@ fks_status fks_host_radial_terms(double gamma, double R, int32_t K, double tol, 
     return FKS_OK;
 }
 
+fks_status fks_host_tables_2d(const fks_plan_desc* desc, int32_t* J_out, double* ab) {
+    if (!J_out) return FKS_ERR_INVALID;
+    fks_plan_desc d{};
+    fks_status st = resolve_desc(desc, &d);
+    if (st != FKS_OK) return st;
+    if (d.dim != 2) return FKS_ERR_INVALID;
+    *J_out = d.n_polar + 1;
+    if (ab) {
+        std::vector<double> t;
+        tables_2d(d, t);
+        std::memcpy(ab, t.data(), t.size() * sizeof(double));
+    }
+    return FKS_OK;
+}
+
+// A dim = 2 plan: host FP64 tables (closed form), uploaded in FP64 and, for
+// FP32 plans, rounded to FP32; 4x4 Gram inverse of the 2D invariants.
+static fks_status plan_create_2d(fks_plan* p) {
+    const fks_plan_desc& d = p->desc;
+    const int n = d.n, A = d.n_polar;
+    p->dim = 2;
+    p->M = A;
+    p->K = 1;
+    p->J = A + 1;
+    p->H = n * n;
+    p->kappa = kPi / d.T;
+    p->dirs.assign((size_t)A * 4, 0.0);
+    for (int q = 1; q <= A; ++q) {
+        double t = kPi * q / A;
+        p->dirs[(q - 1) * 4 + 0] = std::cos(t);
+        p->dirs[(q - 1) * 4 + 1] = std::sin(t);
+        p->dirs[(q - 1) * 4 + 3] = kPi / A;
+    }
+    // 2 (A + 1) real FFTs of n^2 points (A packed inverse pairs, forward, loss)
+    const double nn = (double)n * n;
+    p->flops_per_cell = (2.0 * A + 2.0) * 2.5 * nn * std::log2(nn) + 7.0 * A * nn + 3.0 * nn;
+    std::vector<double> ab;
+    tables_2d(d, ab);
+    const GridConst2 g2 = grid_const2(n, d.T);
+    if (hipMalloc(&p->d_tab64, ab.size() * sizeof(double)) != hipSuccess) return FKS_ERR_NOMEM;
+    p->table_bytes = ab.size() * sizeof(double);
+    if (hipMalloc(&p->d_gc2, sizeof(GridConst2)) != hipSuccess) return FKS_ERR_NOMEM;
+    if (hipMemcpy(p->d_tab64, ab.data(), ab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_gc2, &g2, sizeof(GridConst2), hipMemcpyHostToDevice) != hipSuccess)
+        return FKS_ERR_DEVICE;
+    if (d.precision == FKS_PREC_F32_FIX64) {
+        std::vector<float> ab32(ab.begin(), ab.end());
+        if (hipMalloc(&p->d_tab32, ab32.size() * sizeof(float)) != hipSuccess) return FKS_ERR_NOMEM;
+        p->table_bytes += ab32.size() * sizeof(float);
+        if (hipMemcpy(p->d_tab32, ab32.data(), ab32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            return FKS_ERR_DEVICE;
+    }
+    return FKS_OK;
+}
+
+static void plan_free(fks_plan* p) {
+    if (p->d_tab64) (void)hipFree(p->d_tab64);
+    if (p->d_tab32) (void)hipFree(p->d_tab32);
+    if (p->d_gc) (void)hipFree(p->d_gc);
+    if (p->d_gc2) (void)hipFree(p->d_gc2);
+    delete p;
+}
+
 fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan** out) {
     if (!out) return FKS_ERR_INVALID;
     *out = nullptr;
@@ -313,6 +387,15 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
     p->desc = d;
     const int n = d.n;
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FKS_ERR_DEVICE; }
+    if (d.dim == 2) {
+        st = plan_create_2d(p);
+        if (st != FKS_OK) {
+            plan_free(p);
+            return st;
+        }
+        *out = p;
+        return FKS_OK;
+    }
     p->M = d.n_polar * d.n_azim;
     if (d.gamma == 1.0) {
         p->K = 1;   // constant Carleman kernel: closed-form phi, psi
@@ -370,10 +453,7 @@ fks_status fks_plan_destroy(fks_plan* p) {
     if (!p) return FKS_OK;
     fks_status st = FKS_OK;
     if (hipDeviceSynchronize() != hipSuccess) st = FKS_ERR_DEVICE;
-    if (p->d_tab64) (void)hipFree(p->d_tab64);
-    if (p->d_tab32) (void)hipFree(p->d_tab32);
-    if (p->d_gc) (void)hipFree(p->d_gc);
-    delete p;
+    plan_free(p);
     return st;
 }
 
@@ -389,6 +469,7 @@ fks_status fks_plan_query(const fks_plan* p, fks_plan_info* info) {
     info->fused = p->fused ? 1 : 0;
     info->table_bytes = p->table_bytes;
     info->flops_per_cell = p->flops_per_cell;
+    info->dim = p->dim;
     return FKS_OK;
 }
 
@@ -410,7 +491,8 @@ static fks_status check_segment(const fks_segment& s) {
     if (!std::isfinite(s.dt_over_tau)) return FKS_ERR_INVALID;
     // the kernels move f, q_out and f_out in 16-byte vectors
     if (((uintptr_t)s.f | (uintptr_t)s.q_out | (uintptr_t)s.f_out) & 15u) return FKS_ERR_INVALID;
-    size_t bytes = (size_t)s.ncell * s.plan->desc.n * s.plan->desc.n * s.plan->desc.n * sizeof(double);
+    size_t bytes = (size_t)s.ncell * s.plan->desc.n * s.plan->desc.n * sizeof(double);
+    if (s.plan->dim == 3) bytes *= (size_t)s.plan->desc.n;
     if (s.q_out && s.f_out) {
         const char* a = (const char*)s.q_out;
         const char* b = (const char*)s.f_out;
@@ -430,7 +512,7 @@ static fks_status check_segment(const fks_segment& s) {
 }
 
 static size_t segment_ws(const fks_segment& s) {
-    if (s.ncell == 0) return 0;
+    if (s.ncell == 0 || s.plan->dim == 2) return 0;
     return s.plan->fused ? fused_workspace_bytes(s.plan, s.ncell) : generic_workspace_bytes(s.plan, s.ncell);
 }
 
@@ -460,8 +542,9 @@ fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* worksp
     for (int i = 0; i < nseg; ++i) {
         const fks_segment& g = segs[i];
         if (g.ncell == 0) continue;
-        hipError_t e = g.plan->fused ? collide_fused(g.plan, g, workspace, ws_bytes, s)
-                                     : collide_generic(g.plan, g, workspace, ws_bytes, s);
+        hipError_t e = g.plan->dim == 2 ? collide_2d(g.plan, g, s)
+                       : g.plan->fused ? collide_fused(g.plan, g, workspace, ws_bytes, s)
+                                       : collide_generic(g.plan, g, workspace, ws_bytes, s);
         if (e != hipSuccess) return FKS_ERR_DEVICE;
     }
     return FKS_OK;

@@ -20,6 +20,13 @@ struct GridConst {
     double ginv[25];  // inverse Gram matrix of the scaled basis over the grid (row-major)
 };
 
+// The same for two velocity dimensions: basis (1, v_x/T, v_y/T, |v|^2/T^2).
+struct GridConst2 {
+    double T;
+    double dv;
+    double ginv[16];
+};
+
 // Integer velocity-index shifts of one transport step (per axis, per 1D index).
 struct ShiftTable {
     int8_t s[3][64];
@@ -30,7 +37,7 @@ struct ShiftTable {
 struct fks_plan {
     fks_plan_desc desc;      // with defaults resolved
     int M = 0, K = 0, J = 0; // directions, radial terms, convolution terms (M*K + 1)
-    int H = 0;               // half-spectrum points (n/2+1) n^2
+    int H = 0;               // table points per term: (n/2+1) n^2 (3D), n^2 (2D)
     double kappa = 0.0;      // pi / T
     fks::GridConst gc{};
     std::vector<double> dirs;       // [M][4] (e_x, e_y, e_z, w)
@@ -39,6 +46,8 @@ struct fks_plan {
     double* d_tab64 = nullptr;      // [J][H][2] (omega*alpha, beta) FP64
     float* d_tab32 = nullptr;       // same, rounded to FP32 (FP32 plans only)
     fks::GridConst* d_gc = nullptr; // device copy of gc
+    int dim = 3;                    // velocity dimension
+    fks::GridConst2* d_gc2 = nullptr;   // device grid constants of a dim = 2 plan
     size_t table_bytes = 0;
     bool fused = false;             // fks_collide_batch uses the fused kernel
     int fused_grid = 0;             // persistent grid of the fused kernel
@@ -72,6 +81,12 @@ int fused_grid_size(int n, int device);
 size_t fused_workspace_bytes(const fks_plan* plan, int64_t ncell);
 hipError_t collide_fused(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
                          hipStream_t stream);
+
+// two velocity dimensions (fks_2d.hip)
+bool supported_n_2d(int n, int precision);
+GridConst2 grid_const2(int n, double T);
+void tables_2d(const fks_plan_desc& d, std::vector<double>& ab);   // [J][n][n][2]
+hipError_t collide_2d(const fks_plan* plan, const fks_segment& seg, hipStream_t stream);
 
 // moments, projection, transport (fks_aux.hip)
 GridConst grid_const(int n, double T);

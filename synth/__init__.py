@@ -135,3 +135,35 @@ def blast_density(nc: int, x0=(0.5, 0.5, 0.5)) -> np.ndarray:
     dy = (xc - x0[1])[None, :, None] ** 2
     dx = (xc - x0[0])[None, None, :] ** 2
     return 1.0 + 0.5 * np.exp(-(dx + dy + dz) / 0.01)
+
+
+# ---------------------------------------------------------------- two velocity dimensions
+
+def maxwellian2(n: int, T: float, rho: float, u, theta: float) -> np.ndarray:
+    """rho (2 pi theta)^{-1} exp(-|v-u|^2 / (2 theta)) on the n^2 grid, [x][y]."""
+    v = velocity_nodes(n, T)
+    gx = np.exp(-(v - u[0]) ** 2 / (2 * theta))
+    gy = np.exp(-(v - u[1]) ** 2 / (2 * theta))
+    return rho / (2 * math.pi * theta) * gx[:, None] * gy[None, :]
+
+
+def two_maxwellian_cells_2d(n: int, T: float, ncell: int, seed_offset: int = 20) -> np.ndarray:
+    """f[ncell][n][n] (FP64): per cell a sum of two isotropic two-dimensional
+    Maxwellians, rho ~ U[0.5, 2], theta ~ U[0.5, 2], u ~ N(0, 0.5^2 I2)
+    (the two-Maxwellian shape of the paper's homogeneous tests, in 2D)."""
+    g = rng(seed_offset)
+    rho = g.uniform(0.5, 2.0, size=(ncell, 2))
+    theta = g.uniform(0.5, 2.0, size=(ncell, 2))
+    u = g.normal(0.0, 0.5, size=(ncell, 2, 2))
+    out = np.empty((ncell, n, n), dtype=np.float64)
+    for c in range(ncell):
+        out[c] = (maxwellian2(n, T, rho[c, 0], u[c, 0], theta[c, 0])
+                  + maxwellian2(n, T, rho[c, 1], u[c, 1], theta[c, 1]))
+    return out
+
+
+def bkw2d_initial(n: int, T: float) -> np.ndarray:
+    """Initial datum of the two-dimensional BKW test: |v|^2/pi exp(-|v|^2) on the n^2 grid."""
+    v = velocity_nodes(n, T)
+    v2 = v[:, None] ** 2 + v[None, :] ** 2
+    return v2 / math.pi * np.exp(-v2)

@@ -79,3 +79,40 @@ def test_host_radial_terms_tolerance_selects_K():
     for gamma in (0.0, 0.5):
         k, _, _ = fks.host_radial_terms(gamma, 3.6, K=0, tol=1e-4)
         assert k == O.radial_terms(gamma, 3.6, tol=1e-4).K
+
+
+# -- two velocity dimensions (dim = 2): validation and host tables ------------
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(dim=4), fks.FKS_ERR_INVALID),
+    (dict(dim=2, gamma=1.0), fks.FKS_ERR_UNSUPPORTED),       # only Maxwell molecules decouple in 2D
+    (dict(dim=2, n_azim=4), fks.FKS_ERR_INVALID),
+    (dict(dim=2, n=10), fks.FKS_ERR_UNSUPPORTED),
+    (dict(dim=2, n=64, precision=fks.PREC_F64), fks.FKS_ERR_UNSUPPORTED),
+    (dict(dim=2, flags=fks.FLAG_FORCE_GENERIC), fks.FKS_ERR_UNSUPPORTED),
+    (dict(dim=2, radial_terms=3), fks.FKS_ERR_INVALID),
+])
+def test_desc2d_validation_rejects(kw, expect):
+    base = dict(n=16, T=6.0, gamma=0.0, n_polar=8, n_azim=1)
+    base.update(kw)
+    assert fks.desc_validate(fks.Desc(**base)) == expect
+
+
+@pytest.mark.parametrize("n,prec", [(8, fks.PREC_F64), (12, fks.PREC_F64), (32, fks.PREC_F64),
+                                    (48, fks.PREC_F32_FIX64), (64, fks.PREC_F32_FIX64)])
+def test_desc2d_validation_accepts(n, prec):
+    assert fks.desc_validate(fks.desc2d(n, 6.0, 8, prec)) == fks.FKS_OK
+
+
+@pytest.mark.parametrize("n,T,A", [(8, 4.0, 8), (16, 6.0, 5), (24, 9.0, 16)])
+def test_host_tables_2d_match_oracle(n, T, A):
+    # the library's host tables against the oracle's alpha, alpha', omega and L (eq. dfor0)
+    import oracle.fks_oracle2d as O2
+    ab = fks.host_tables_2d(fks.desc2d(n, T, A))
+    p = O2.make_plan2(n, T, A)
+    assert ab.shape == (A + 1, n, n, 2)
+    gain = ab[:A, ..., 0] * ab[:A, ..., 1]
+    assert np.allclose(gain, p.omega * p.alpha * p.alphap, rtol=0, atol=1e-13 * p.R * p.R)
+    assert np.allclose(ab[:A, ..., 0] ** 2, p.omega * p.alpha ** 2, rtol=0, atol=1e-13 * p.R * p.R)
+    assert np.allclose(ab[A, ..., 0] * ab[A, ..., 1], -p.loss, rtol=0, atol=1e-13 * np.abs(p.loss).max())
+    assert np.all(ab[A, ..., 1] == ab[A, 0, 0, 1]) and ab[A, 0, 0, 1] > 0

@@ -1,0 +1,125 @@
+"""Two velocity dimensions (Maxwell molecules, Section 3.3 eq. dfor0) on the GPU
+against the oracle: per-cell parity of Q_c over several workgroups and a ragged
+tail, the update, Test 1.1's trajectory, and mixed 2D / 3D batches."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.fks_oracle2d as O2
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1608_08009_amd as fks  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _ref(f, n, T, A):
+    p = O2.make_plan2(n, T, A)
+    out, ratio = [], []
+    for c in f:
+        Q, _, loss = O2.collide2_fast64(c, p, parts=True)
+        qc = O2.conserve2_Q(Q, n, T)
+        out.append(qc)
+        ratio.append(np.linalg.norm(loss) / np.linalg.norm(qc))
+    return np.stack(out), np.array(ratio)
+
+
+# cells per workgroup of the 2D kernel: 256/n, or fewer when LDS-limited; the
+# counts below cover several workgroups and a partial last one
+CASES = [(8, 4.0, 8, 71), (12, 5.0, 8, 45), (16, 6.0, 8, 37), (24, 8.0, 16, 23), (32, 9.0, 8, 19),
+         (48, 10.0, 8, 11), (64, 12.0, 8, 7)]
+
+
+# FP64 2D plans stop at n = 32 (register budget); FP32 plans go to n = 64
+PARAMS = [(c, prec) for c in CASES for prec in (fks.PREC_F64, fks.PREC_F32_FIX64)
+          if prec == fks.PREC_F32_FIX64 or c[0] <= 32]
+
+
+@pytest.mark.parametrize("case,prec", PARAMS)
+def test_collide2d_matches_oracle(case, prec):
+    n, T, A, ncell = case
+    f = synth.two_maxwellian_cells_2d(n, T, ncell, seed_offset=40 + n)
+    ref, ratio = _ref(f, n, T, A)
+    with fks.Plan(fks.desc2d(n, T, A, prec)) as plan:
+        assert plan.info.dim == 2 and plan.info.J == A + 1
+        q = torch.empty((ncell, n, n), dtype=torch.float64, device="cuda")
+        fks.collide(plan, _dev(f), q_out=q)
+        torch.cuda.synchronize()
+        got = q.cpu().numpy()
+    per = np.array([np.linalg.norm(got[c] - ref[c]) / np.linalg.norm(ref[c]) for c in range(ncell)])
+    if prec == fks.PREC_F64:
+        assert per.max() <= 1e-12, per.max()
+    else:
+        assert np.all(per <= 1.5e-6 * (1.0 + ratio)), (per.max(), ratio[per.argmax()])
+        agg = np.sqrt(np.sum((got - ref) ** 2) / np.sum(ref ** 2))
+        assert agg <= 1e-5
+    # conservation of the projected operator (invariants 1, v, |v|^2), FP64 fix
+    m = O2.moments2(got, n, T)
+    v = O2.velocity_grid2(n, T)
+    w = np.stack([np.ones((n, n)), np.abs(v)[:, None] * np.ones((1, n)),
+                  np.ones((n, 1)) * np.abs(v)[None, :], v[:, None] ** 2 + v[None, :] ** 2])
+    scale = (2 * T / n) ** 2 * np.einsum("cxy,axy->ca", np.abs(got), w)
+    assert np.all(np.abs(m) <= 1e-12 * scale)
+
+
+def test_collide2d_update_in_place_and_empty():
+    n, T, A, ncell = 16, 6.0, 8, 40
+    f = synth.two_maxwellian_cells_2d(n, T, ncell, seed_offset=77)
+    ref, _ = _ref(f, n, T, A)
+    dt = 0.05
+    with fks.Plan(fks.desc2d(n, T, A, fks.PREC_F64)) as plan:
+        fd = _dev(f)
+        out = torch.empty_like(fd)
+        fks.collide(plan, fd, f_out=out, dt_over_tau=dt)
+        fks.collide(plan, fd, f_out=fd, dt_over_tau=dt)        # in place
+        torch.cuda.synchronize()
+        for g in (out, fd):
+            assert np.max(np.abs(g.cpu().numpy() - (f + dt * ref))) <= 1e-13 * np.max(f)
+        empty = torch.empty((0, n, n), dtype=torch.float64, device="cuda")
+        fks.collide(plan, empty, q_out=empty)                 # ncell = 0
+        assert fks.workspace_size([(plan, fd, None, fd, ncell, dt)]) == 0
+
+
+@pytest.mark.parametrize("prec,tol", [(fks.PREC_F64, 1e-10), (fks.PREC_F32_FIX64, 2e-5)])
+def test_test11_trajectory_matches_oracle(prec, tol):
+    # Test 1.1 (Section 5.1) at 16^2 on [-6, 6]^2: 500 explicit steps of dt = 0.02, 8 angles
+    n, T, A, dt, steps = 16, 6.0, 8, 0.02, 500
+    f0 = synth.bkw2d_initial(n, T)
+    p = O2.make_plan2(n, T, A)
+    g = f0.copy()
+    for _ in range(steps):
+        g = g + dt * O2.conserve2_Q(O2.collide2_fast64(g, p), n, T)
+    with fks.Plan(fks.desc2d(n, T, A, prec)) as plan:
+        f = _dev(f0[None])
+        for _ in range(steps):
+            fks.collide(plan, f, f_out=f, dt_over_tau=dt)
+        torch.cuda.synchronize()
+        got = f[0].cpu().numpy()
+    assert np.linalg.norm(got - g) <= tol * np.linalg.norm(g)
+    ex = O2.bkw2d(n, T, steps * dt)
+    l1 = np.sum(np.abs(got - ex)) / np.sum(ex)
+    l1_or = np.sum(np.abs(g - ex)) / np.sum(ex)
+    assert abs(l1 - l1_or) <= 1e-3 * l1_or + tol
+
+
+def test_mixed_2d_and_3d_batch():
+    # one fks_collide_batch call with a 2D and a 3D segment
+    n2, T2, n3, T3 = 32, 9.0, 16, 8.0
+    f2 = synth.two_maxwellian_cells_2d(n2, T2, 9, seed_offset=91)
+    f3 = synth.two_maxwellian_cells(n3, T3, 3, seed_offset=92)
+    ref2, _ = _ref(f2, n2, T2, 8)
+    op3 = O.make_plan(n3, T3)
+    ref3 = np.stack([O.conserve_Q(O.collide_fast64(c, op3), n3, T3) for c in f3])
+    with fks.Plan(fks.desc2d(n2, T2, 8, fks.PREC_F64)) as p2, \
+            fks.Plan(fks.Desc(n=n3, T=T3, precision=fks.PREC_F64)) as p3:
+        a, b = _dev(f2), _dev(f3)
+        qa, qb = torch.empty_like(a), torch.empty_like(b)
+        fks.collide_batch([(p2, a, qa, None, 9, 0.0), (p3, b, qb, None, 3, 0.0)])
+        torch.cuda.synchronize()
+        assert np.max(np.abs(qa.cpu().numpy() - ref2)) <= 1e-12 * np.max(np.abs(ref2))
+        assert np.max(np.abs(qb.cpu().numpy() - ref3)) <= 1e-12 * np.max(np.abs(ref3))
