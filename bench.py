@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=512, help="cells timed on the CPU oracle (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="skip the BGK and two-dimensional timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 512 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -183,6 +185,53 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # BGK relaxation (conservative discrete Maxwellian) on the same batch: HBM-bound
+    bgk_line = None
+    if args.extras:
+        nu_mu = 4.0 * math.pi * plan.info.c_gamma * (2.0 * plan.info.R)   # mu for hard spheres
+        fks.bgk(fa, N_V, T_BOX, nu_mu, dim=3, f_out=fb, dt_over_tau=DT_OVER_TAU)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fks.bgk(fa, N_V, T_BOX, nu_mu, dim=3, f_out=fb, dt_over_tau=DT_OVER_TAU)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_bgk = e0.elapsed_time(e1) / args.steps
+        alg = NCELL * N_V ** 3 * 16.0            # read f, write f_out (FP64)
+        bgk_line = {"workload": f"{NCELL} cells, 32^3, 3D, nu = mu, Euler step, f_out", "ms": round(ms_bgk, 4),
+                    "value": NCELL * N_V ** 3 / (ms_bgk * 1e-3), "unit": UNIT,
+                    "roofline": {"bound": "hbm", "achieved": round(alg / (ms_bgk * 1e-3) / 1e9, 1),
+                                 "peak": 8000.0, "unit": "GB/s",
+                                 "frac": round(alg / (ms_bgk * 1e-3) / 8e12, 4), "bytes_per_launch": alg}}
+        print(f"[bench] bgk: {ms_bgk:.3f} ms per batch", file=sys.stderr, flush=True)
+
+    # two velocity dimensions: Maxwell molecules, 8192 cells of 32^2, A = 8 (Test 1.1 resolution)
+    d2_line = None
+    if args.extras:
+        n2, T2, c2 = 32, 9.0, 8192
+        f2 = torch.as_tensor(synth.two_maxwellian_cells_2d(n2, T2, c2, seed_offset=123), device=dev)
+        g2 = torch.empty_like(f2)
+        d2_line = {}
+        for prec, name in ((fks.PREC_F64, "f64"), (fks.PREC_F32_FIX64, "f32+f64fix")):
+            with fks.Plan(fks.desc2d(n2, T2, 8, prec)) as p2:
+                fks.collide(p2, f2, f_out=g2, dt_over_tau=0.02)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    fks.collide(p2, f2, f_out=g2, dt_over_tau=0.02)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms2 = e0.elapsed_time(e1) / args.steps
+                fl = p2.info.flops_per_cell * c2 / (ms2 * 1e-3) / 1e12
+                d2_line[name] = {"ms": round(ms2, 4), "value": c2 * n2 * n2 / (ms2 * 1e-3),
+                                 "unit": "cells·N²/s", "algorithmic_tflops": round(fl, 2)}
+        d2_line["workload"] = f"{c2} cells, 2D Maxwell molecules, 32^2 on [-9,9]^2, A = 8, f_out"
+        del f2, g2
+        print(f"[bench] 2d: {d2_line['f64']['ms']:.3f} ms (f64), {d2_line['f32+f64fix']['ms']:.3f} ms (f32)",
+              file=sys.stderr, flush=True)
+
     # plain FP64 path (multi-pass), same workload
     fp64 = None
     if args.fp64_steps > 0:
@@ -246,6 +295,8 @@ def main():
         "cpu_baseline": cpu,
         "fp64_path": fp64,
         "parity": parity,
+        "bgk": bgk_line,
+        "collide2d": d2_line,
     }
     print(json.dumps(line), flush=True)
 

@@ -231,6 +231,38 @@ fks_status fks_profile_last(double* kernel_ms, int32_t capacity, int32_t* count)
 const char* fks_status_string(fks_status status);
 
 /*
+ * BGK relaxation operator with the conservative discrete Maxwellian
+ * (Section 2 eq. ibgk; Section 3.2 eq. minimMax), FP64, per cell:
+ *   U = C f;  (rho, u, theta) with d_v rho theta = sum |v|^2 f dv^d - rho |u|^2;
+ *   M~ = rho (2 pi theta)^{-d/2} exp(-|v-u|^2 / (2 theta)) at the nodes;
+ *   E = M~ + C^T (C C^T)^{-1} (U - C M~), so that C E = U exactly;
+ *   Q = nu' (E - f) with nu' = nu (nu_rho = 0) or nu * rho (nu_rho = 1).
+ * Outputs: q_out = Q; f_out = f + dt_over_tau Q (step FKS_BGK_EULER, eq. f_coll)
+ * or E + exp(-nu' dt_over_tau) (f - E) (FKS_BGK_EXACT, the exact solution of
+ * df/dt = nu'(E - f) with E fixed).  A cell with rho <= 0 or theta <= 0 has no
+ * Maxwellian and is left unchanged (Q = 0).
+ *   f      device, const, [ncell][n^dim] FP64 (same layout as fks_collide_batch)
+ *   q_out  device [ncell][n^dim] or NULL; must not overlap f or f_out
+ *   f_out  device [ncell][n^dim] or NULL; may alias f
+ * dim 3: 2 <= n <= 64; dim 2: 2 <= n <= 512.  No workspace.  Asynchronous on
+ * hip_stream.  Errors: FKS_ERR_INVALID (NULL desc or f, both outputs NULL,
+ * overlaps, out-of-range fields, ncell < 0), FKS_ERR_DEVICE.
+ */
+typedef enum { FKS_BGK_EULER = 0, FKS_BGK_EXACT = 1 } fks_bgk_step;
+
+typedef struct {
+    int32_t dim;      /* 2 or 3 */
+    int32_t n;        /* velocity points per axis */
+    double  T;        /* grid on [-T, T)^dim */
+    double  nu;       /* collision frequency, or its factor when nu_rho = 1 (>= 0) */
+    int32_t nu_rho;   /* 0: nu' = nu; 1: nu' = nu * rho */
+    int32_t step;     /* fks_bgk_step */
+} fks_bgk_desc;
+
+fks_status fks_bgk(const fks_bgk_desc* desc, const double* f, double* q_out, double* f_out,
+                   int64_t ncell, double dt_over_tau, void* hip_stream);
+
+/*
  * Host-only helpers (no device needed), exposed so that the host precompute
  * can be checked without a GPU.
  *   fks_desc_validate: the validation fks_plan_create performs.

@@ -28,6 +28,8 @@ PREC_F32_FIX64 = 1
 RULE_GAUSS = 0
 RULE_MIDPOINT = 1
 FLAG_FORCE_GENERIC = 0x1
+BGK_EULER = 0
+BGK_EXACT = 1
 BC_PERIODIC = 0
 BC_DIRICHLET = 1
 
@@ -36,7 +38,7 @@ EXPORTED = [
     "fks_workspace_size", "fks_collide_batch", "fks_moments", "fks_conserve",
     "fks_transport_shift", "fks_status_string", "fks_desc_validate",
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
-    "fks_host_tables_2d",
+    "fks_host_tables_2d", "fks_bgk",
 ]
 
 
@@ -62,6 +64,13 @@ class Segment(C.Structure):
     _fields_ = [
         ("plan", C.c_void_p), ("f", C.c_void_p), ("q_out", C.c_void_p), ("f_out", C.c_void_p),
         ("ncell", C.c_int64), ("dt_over_tau", C.c_double),
+    ]
+
+
+class BgkDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32), ("T", C.c_double), ("nu", C.c_double),
+        ("nu_rho", C.c_int32), ("step", C.c_int32),
     ]
 
 
@@ -101,6 +110,7 @@ def lib() -> C.CDLL:
     L.fks_profile_enable.argtypes = [i32]
     L.fks_profile_last.argtypes = [vp, i32, C.POINTER(i32)]
     L.fks_host_tables_2d.argtypes = [C.POINTER(PlanDesc), C.POINTER(i32), vp]
+    L.fks_bgk.argtypes = [C.POINTER(BgkDesc), vp, vp, vp, i64, dbl, vp]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -324,6 +334,27 @@ def transport_shift(f_in, f_out, nx: int, ny: int, nz: int, dx: float, bc, n: in
     _check(lib().fks_transport_shift(C.c_void_p(_ptr(f_in)), C.c_void_p(_ptr(f_out)), C.byref(sp), n, T, dt,
                                      C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(bc_f)),
                                      C.c_void_p(_stream_ptr(stream))), "fks_transport_shift")
+
+
+def bgk(f, n: int, T: float, nu: float, dim: int = 3, q_out=None, f_out=None, dt_over_tau: float = 0.0,
+        nu_rho: bool = False, step: int = BGK_EULER, stream=None):
+    """BGK relaxation with the conservative discrete Maxwellian (fks_bgk); f is
+    [ncell, n^dim] float64 on the GPU (any shape with that many elements)."""
+    cs = n ** dim
+    ncell = f.numel() // cs
+    _require_device_f64(f, "f", ncell * cs)
+    _require_device_f64(q_out, "q_out", ncell * cs)
+    _require_device_f64(f_out, "f_out", ncell * cs)
+    d = BgkDesc(dim, n, T, nu, 1 if nu_rho else 0, step)
+    _check(lib().fks_bgk(C.byref(d), C.c_void_p(_ptr(f)), C.c_void_p(_ptr(q_out)), C.c_void_p(_ptr(f_out)),
+                         ncell, dt_over_tau, C.c_void_p(_stream_ptr(stream))), "fks_bgk")
+
+
+def bgk_validate(dim: int, n: int, T: float, nu: float, nu_rho: int = 0, step: int = BGK_EULER,
+                 dt_over_tau: float = 0.0) -> int:
+    """Status of fks_bgk on an empty batch (argument validation only, no device work)."""
+    d = BgkDesc(dim, n, T, nu, nu_rho, step)
+    return lib().fks_bgk(C.byref(d), None, None, None, 0, dt_over_tau, None)
 
 
 def profile_enable(on: bool = True) -> None:

@@ -564,6 +564,29 @@ fks_status fks_conserve(double* f, const double* U, int64_t ncell, int32_t n, do
     return conserve(f, U, ncell, n, T, (hipStream_t)hip_stream) == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
 }
 
+fks_status fks_bgk(const fks_bgk_desc* d, const double* f, double* q_out, double* f_out, int64_t ncell,
+                   double dt_over_tau, void* hip_stream) {
+    if (!d || ncell < 0 || !std::isfinite(dt_over_tau)) return FKS_ERR_INVALID;
+    if (d->dim != 2 && d->dim != 3) return FKS_ERR_INVALID;
+    if (d->n < 2 || d->n > (d->dim == 3 ? 64 : 512)) return FKS_ERR_INVALID;
+    if (!(d->T > 0) || !std::isfinite(d->T) || !(d->nu >= 0) || !std::isfinite(d->nu)) return FKS_ERR_INVALID;
+    if ((d->nu_rho != 0 && d->nu_rho != 1) || (d->step != FKS_BGK_EULER && d->step != FKS_BGK_EXACT))
+        return FKS_ERR_INVALID;
+    if (ncell == 0) return FKS_OK;
+    if (!f || (!q_out && !f_out)) return FKS_ERR_INVALID;
+    size_t bytes = (size_t)ncell * d->n * d->n * sizeof(double);
+    if (d->dim == 3) bytes *= (size_t)d->n;
+    auto overlap = [bytes](const void* x, const void* y) {
+        const char* a = (const char*)x;
+        const char* b = (const char*)y;
+        return x && y && a < b + bytes && b < a + bytes;
+    };
+    if (overlap(q_out, f) || overlap(q_out, f_out)) return FKS_ERR_INVALID;
+    if (f_out && f_out != f && overlap(f_out, f)) return FKS_ERR_INVALID;
+    return bgk(*d, f, q_out, f_out, ncell, dt_over_tau, (hipStream_t)hip_stream) == hipSuccess ? FKS_OK
+                                                                                             : FKS_ERR_DEVICE;
+}
+
 fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_space_desc* sp, int32_t n,
                                double T, double dt, double* offsets, const double* bc_f, void* hip_stream) {
     if (!f_in || !f_out || !sp || !offsets) return FKS_ERR_INVALID;

@@ -88,6 +88,10 @@ GridConst2 grid_const2(int n, double T);
 void tables_2d(const fks_plan_desc& d, std::vector<double>& ab);   // [J][n][n][2]
 hipError_t collide_2d(const fks_plan* plan, const fks_segment& seg, hipStream_t stream);
 
+// BGK relaxation (fks_bgk.hip)
+hipError_t bgk(const fks_bgk_desc& d, const double* f, double* q_out, double* f_out, int64_t ncell,
+               double dt_over_tau, hipStream_t stream);
+
 // moments, projection, transport (fks_aux.hip)
 GridConst grid_const(int n, double T);
 hipError_t moments(const double* f, int64_t ncell, int n, double T, double* U, hipStream_t stream);

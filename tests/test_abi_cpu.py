@@ -116,3 +116,24 @@ def test_host_tables_2d_match_oracle(n, T, A):
     assert np.allclose(ab[:A, ..., 0] ** 2, p.omega * p.alpha ** 2, rtol=0, atol=1e-13 * p.R * p.R)
     assert np.allclose(ab[A, ..., 0] * ab[A, ..., 1], -p.loss, rtol=0, atol=1e-13 * np.abs(p.loss).max())
     assert np.all(ab[A, ..., 1] == ab[A, 0, 0, 1]) and ab[A, 0, 0, 1] > 0
+
+
+# -- BGK (fks_bgk): argument validation, no device work -----------------------
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(), fks.FKS_OK),
+    (dict(dim=2, n=512), fks.FKS_OK),
+    (dict(dim=4), fks.FKS_ERR_INVALID),
+    (dict(n=1), fks.FKS_ERR_INVALID),
+    (dict(n=65), fks.FKS_ERR_INVALID),
+    (dict(dim=2, n=513), fks.FKS_ERR_INVALID),
+    (dict(T=0.0), fks.FKS_ERR_INVALID),
+    (dict(nu=-1.0), fks.FKS_ERR_INVALID),
+    (dict(nu_rho=2), fks.FKS_ERR_INVALID),
+    (dict(step=5), fks.FKS_ERR_INVALID),
+    (dict(dt_over_tau=float("nan")), fks.FKS_ERR_INVALID),
+])
+def test_bgk_validation(kw, expect):
+    args = dict(dim=3, n=32, T=8.0, nu=1.0)
+    args.update(kw)
+    assert fks.bgk_validate(**args) == expect
