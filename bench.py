@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cells·N³/s of Q(f,f) at N=32³, M=32 (FP32+fix vs FP64, rel err ≤1e-5)"
 UNIT = "cells·N³/s"
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X dense FP32 vector (packed) peak
+PEAK_FP32_UNPACKED_TFLOPS = 78.6    # without packed FP32 (disabled in this build): 256 CU x 64 lanes x 2 x 2.4 GHz
 N_V, T_BOX, NCELL = 32, 8.0, 4096
 N_POLAR, N_AZIM = 8, 4
 DT_OVER_TAU = 1e-3
@@ -106,6 +107,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=512, help="cells timed on the CPU oracle (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--eager", dest="graph", action="store_false",
+                    help="launch each step directly instead of replaying captured graphs")
     ap.add_argument("--no-extras", dest="extras", action="store_false",
                     help="skip the BGK and two-dimensional timings")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -142,25 +145,45 @@ def main():
     def step(src, dst):
         fks.collide_batch([(plan, src, None, dst, NCELL, DT_OVER_TAU)], workspace=ws)
 
+    # one time step in each direction of the f ping-pong, captured as graphs and replayed
+    graphs = []
+    if args.graph:
+        cap = torch.cuda.Stream()
+        cap.wait_stream(stream)
+        for src, dst in ((fa, fb), (fb, fa)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                step(src, dst)
+            graphs.append(g)
+        torch.cuda.synchronize()
+
+    def run(i):
+        if graphs:
+            graphs[i % 2].replay()
+        elif i % 2 == 0:
+            step(fa, fb)
+        else:
+            step(fb, fa)
+
     for i in range(args.warmup):
-        step(fa, fb)
-        fa, fb = fb, fa
+        run(i)
     torch.cuda.synchronize()
-    print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
+    print(f"[bench] warmup done; timing {args.steps} steps ({'graph replay' if graphs else 'eager'})",
+          file=sys.stderr, flush=True)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     t_start.record(stream)
     for i in range(args.steps):
         ev[i][0].record(stream)
-        step(fa, fb)
+        run(args.warmup + i)
         ev[i][1].record(stream)
-        fa, fb = fb, fa
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     launch_ms = [a.elapsed_time(b) for a, b in ev]
     ms_per_step = total_ms / args.steps
     avg_call_ms = sum(launch_ms) / len(launch_ms)
+    median_ms = sorted(launch_ms)[len(launch_ms) // 2]
     value = NCELL * N_V ** 3 / (ms_per_step * 1e-3)
     # per-kernel durations (HIP events recorded by the library on this stream)
     fks.profile_enable(True)
@@ -277,6 +300,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_median": round(median_ms, 4),
+        "timing": ("hipGraph replay of one captured step per ping-pong direction" if graphs else "eager launches")
+                  + "; ms_per_step = total of the timed steps / steps",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -288,6 +314,8 @@ def main():
                    "R": plan.info.R, "dt_over_tau": DT_OVER_TAU, "terms_per_cell": plan.info.J},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "peak_unpacked_fma": PEAK_FP32_UNPACKED_TFLOPS,
+                     "frac_unpacked_fma": round(achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4),
                      "traffic": _traffic_per_launch(), "kernel": "k_terms<32>",
                      "avg_launch_ms": round(terms_ms, 4), "finish_kernel_ms": round(finish_ms, 4),
                      "call_ms": round(avg_call_ms, 4), "flops_per_cell": plan.info.flops_per_cell,

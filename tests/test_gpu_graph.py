@@ -1,0 +1,57 @@
+"""The batched calls under graph capture: each captured call is replayed several
+times, with eager work and synchronisations between the replays, and every
+replay must reproduce the eager result bit for bit (the kernels are
+deterministic and allocate nothing)."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1608_08009_amd as fks  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _replays_match(call, outs, nrep=3):
+    for o in outs:
+        o.fill_(0.0)
+    call()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cap):
+        call()
+    torch.cuda.synchronize()
+    for _ in range(nrep):
+        for o in outs:
+            o.fill_(-1.0)                      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e)
+
+
+@pytest.mark.parametrize("n,prec", [(32, fks.PREC_F32_FIX64), (16, fks.PREC_F64), (24, fks.PREC_F32_FIX64)])
+def test_collide_batch_graph_replay(n, prec):
+    f = torch.as_tensor(synth.two_maxwellian_cells(n, 8.0, 21, seed_offset=130 + n), device="cuda")
+    q = torch.empty_like(f)
+    g = torch.empty_like(f)
+    with fks.Plan(fks.Desc(n=n, T=8.0, precision=prec)) as plan:
+        seg = [(plan, f, q, g, 21, 0.01)]
+        ws = torch.empty(max(fks.workspace_size(seg), 1), dtype=torch.uint8, device="cuda")
+        _replays_match(lambda: fks.collide_batch(seg, workspace=ws), [q, g])
+
+
+def test_collide2d_and_bgk_graph_replay():
+    f2 = torch.as_tensor(synth.two_maxwellian_cells_2d(32, 9.0, 17, seed_offset=140), device="cuda")
+    f3 = torch.as_tensor(synth.two_maxwellian_cells(32, 8.0, 5, seed_offset=141), device="cuda")
+    q2, q3, g3 = torch.empty_like(f2), torch.empty_like(f3), torch.empty_like(f3)
+    with fks.Plan(fks.desc2d(32, 9.0, 8, fks.PREC_F64)) as p2:
+        def call():
+            fks.collide(p2, f2, q_out=q2)
+            fks.bgk(f3, 32, 8.0, 0.8, dim=3, q_out=q3, f_out=g3, dt_over_tau=0.1, nu_rho=True)
+        _replays_match(call, [q2, q3, g3])
