@@ -44,7 +44,8 @@
 // conflicts; every LDS access is a per-thread base plus an immediate offset).
 // A <-> B only swaps (lane, register) inside the n threads sharing hi: it goes
 // through that group's own block (row = the pencil's ky, column = z) and needs
-// no workgroup barrier.  B <-> C
+// no workgroup barrier when n divides 64 (the group lies in one wave); for
+// n = 24 groups straddle waves and the exchange uses workgroup barriers.  B <-> C
 // crosses waves: P rounds of n^3/P^2 values with workgroup barriers; in every
 // round each group reads back only its own block, so the next group-local
 // exchange can reuse that block without a barrier.
@@ -62,12 +63,26 @@ struct Cfg<8> { static constexpr int P = 1; };
 template <>
 struct Cfg<16> { static constexpr int P = 1; };
 template <>
+struct Cfg<24> { static constexpr int P = 1; };
+template <>
 struct Cfg<32> { static constexpr int P = 2; };
+
+// ordering for the group-local A <-> B exchange: a group of n threads lies in
+// one wave when n divides 64; otherwise (n = 24) groups straddle waves and the
+// whole workgroup synchronises
+template <int N>
+__device__ __forceinline__ void group_sync();
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (64 % N == 0) wave_sync();
+    else __syncthreads();
 }
 
 // Hides a value from loop-invariant code motion so that per-thread address
@@ -96,7 +111,7 @@ __device__ __forceinline__ int kx_of(int p, int hi) {
 template <int N, int P>
 __device__ __forceinline__ int ky_of(int p, int hi, int lo) {
     if (P == 1 || p == 0 || hi == 0) return lo;
-    return (N - lo) & (N - 1);
+    return (N - lo) % N;
 }
 // forward C -> B, round r: LDS block receiving spectral row x (the reader's hi)
 template <int N, int P, int R, int X>
@@ -185,14 +200,14 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
                 constexpr int ky = decltype(kI)::value;
                 blk[ky * RS + lo] = bb[p][ky];
             });
-            wave_sync();
+            group_sync<N>();
             cx<float> a[N];
             const cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // this pencil's actual ky
             sfor<N>([&](auto zI) {
                 constexpr int z = decltype(zI)::value;
                 a[z] = arow[z];
             });
-            wave_sync();
+            group_sync<N>();
             fft<float, N, -1>(a);
             const int kx = kx_of<N, P>(p, hi), ky = ky_of<N, P>(p, hi, lo);
             const float s = ((kx == N / 2) || (ky == N / 2)) ? 0.0f : 1.0f / (float)N3;
@@ -229,7 +244,7 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             const cx<float>* tj = A.tab + (size_t)j * H;
             cx<float> za[P][N];
             // mirror pencil (-hi, -lo), kz in [0, n/2)
-            const int ob = opaque(((N - hi) & (N - 1)) * N + ((N - lo) & (N - 1)));
+            const int ob = opaque(((N - hi) % N) * N + ((N - lo) % N));
             sfor<N / 2>([&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
                 constexpr uint32_t zo = kz * NN * sizeof(cx<float>);
@@ -256,16 +271,19 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
                 fft<float, N, 1>(za[p]);
                 __builtin_amdgcn_sched_barrier(0);
                 cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // row = this pencil's actual ky
+                // a group that straddles waves must not overwrite the block before all of
+                // its threads have read their columns of the previous B -> C round
+                if constexpr (64 % N != 0) __syncthreads();
                 sfor<N>([&](auto zI) {
                     constexpr int z = decltype(zI)::value;
                     arow[z] = za[p][z];
                 });
-                wave_sync();
+                group_sync<N>();
                 sfor<N>([&](auto kI) {
                     constexpr int ky = decltype(kI)::value;
                     zb[p][ky] = blk[ky * RS + lo];
                 });
-                wave_sync();
+                group_sync<N>();
                 fft<float, N, 1>(zb[p]);
             });
             cx<float> zc[P][N];
@@ -322,7 +340,10 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
 // (16-byte partial loads, 32-byte f loads and stores): its (y, z) are fixed
 // and x advances by 4 FT / n^2 per step.
 template <int N>
-constexpr int finish_threads() { return N * N * N / 4 < 512 ? N * N * N / 4 : 512; }
+constexpr int finish_threads() {
+    if constexpr (N == 24) return 576;   // a multiple of 64 and of n^2/4 that divides n^3/4
+    else return N * N * N / 4 < 512 ? N * N * N / 4 : 512;
+}
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
@@ -507,12 +528,13 @@ hipError_t profile_last(double* ms, int cap, int* count) {
     return hipSuccess;
 }
 
-bool fused_available(int n) { return n == 8 || n == 16 || n == 32; }
+bool fused_available(int n) { return n == 8 || n == 16 || n == 24 || n == 32; }
 
 int fused_grid_size(int n, int device) {
     switch (n) {
         case 8: return grid_for<8>(device);
         case 16: return grid_for<16>(device);
+        case 24: return grid_for<24>(device);
         case 32: return grid_for<32>(device);
         default: return 0;
     }
@@ -525,6 +547,7 @@ hipError_t collide_fused(const fks_plan* p, const fks_segment& s, void* ws, size
     switch (p->desc.n) {
         case 8: return launch<8>(p, s, ws, st);
         case 16: return launch<16>(p, s, ws, st);
+        case 24: return launch<24>(p, s, ws, st);
         case 32: return launch<32>(p, s, ws, st);
         default: return hipErrorInvalidValue;
     }

@@ -167,3 +167,27 @@ def bkw2d_initial(n: int, T: float) -> np.ndarray:
     v = velocity_nodes(n, T)
     v2 = v[:, None] ** 2 + v[None, :] ** 2
     return v2 / math.pi * np.exp(-v2)
+
+
+# ---------------------------------------------------------------- full-size workload recipes
+
+UNEVEN_N = (16, 24, 32, 48)
+UNEVEN_SPLIT = {16: (4, 4), 32: (8, 4), 64: (8, 8)}     # M -> (polar, azimuthal) nodes
+UNEVEN_GAMMA = (0.0, 0.5, 1.0)
+
+
+def uneven_batch_draws(ncell: int = 2048, seed_offset: int = 3):
+    """Per-cell (n, M, gamma) drawn uniformly from {16, 24, 32, 48} x {16, 32, 64}
+    x {0, 0.5, 1} (the uneven-batch workload); returns three int/float arrays."""
+    g = rng(seed_offset)
+    n = np.array(UNEVEN_N)[g.integers(0, 4, size=ncell)]
+    M = np.array((16, 32, 64))[g.integers(0, 3, size=ncell)]
+    gamma = np.array(UNEVEN_GAMMA)[g.integers(0, 3, size=ncell)]
+    return n, M, gamma
+
+
+def blast_cell(n: int, T: float, rho: float, cell: int, seed_offset: int = 5) -> np.ndarray:
+    """One cell of the 3D x 3D blast: rho times the unit Maxwellian times (1 + 0.01 xi),
+    xi ~ N(0, 1) per velocity node, drawn from a generator seeded per cell."""
+    g = rng(10_000_000 * seed_offset + cell)
+    return maxwellian(n, T, rho, (0.0, 0.0, 0.0), 1.0) * (1.0 + 0.01 * g.normal(size=(n, n, n)))

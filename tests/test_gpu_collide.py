@@ -156,12 +156,12 @@ def test_collide_f64_vhs_k_terms(gamma, K):
 
 # ---------------------------------------------------------------- FP32 + FP64 fix
 
-@pytest.mark.parametrize("n,ncell,generic", [(8, 9, False), (16, 5, False), (32, 6, False),
+@pytest.mark.parametrize("n,ncell,generic", [(8, 9, False), (16, 5, False), (24, 7, False), (32, 6, False),
                                              (8, 4, True), (12, 3, True), (24, 2, True), (32, 2, True)])
 def test_collide_f32_matches_oracle(n, ncell, generic):
     flags = fks.FLAG_FORCE_GENERIC if generic else 0
     plan = _plan(n=n, T=T_BOX, precision=fks.PREC_F32_FIX64, flags=flags)
-    assert plan.info.fused == (0 if generic or n not in (8, 16, 32) else 1)
+    assert plan.info.fused == (0 if generic or n not in (8, 16, 24, 32) else 1)
     op = _oplan(n, T_BOX, 1.0, 8, 4, 0)
     f = synth.two_maxwellian_cells(n, T_BOX, ncell, seed_offset=200 + n)
     q, _ = _gpu_qc(plan, f)
@@ -170,11 +170,12 @@ def test_collide_f32_matches_oracle(n, ncell, generic):
     _conservation_ok(q, n, T_BOX)
 
 
-def test_collide_f32_vhs_k_terms_fused():
-    n = 16
+@pytest.mark.parametrize("n,ncell", [(16, 3), (24, 5)])
+def test_collide_f32_vhs_k_terms_fused(n, ncell):
     plan = _plan(n=n, T=T_BOX, gamma=0.5, radial_terms=4, precision=fks.PREC_F32_FIX64)
+    assert plan.info.fused == 1
     op = _oplan(n, T_BOX, 0.5, 8, 4, 4)
-    f = synth.two_maxwellian_cells(n, T_BOX, 3, seed_offset=41)
+    f = synth.two_maxwellian_cells(n, T_BOX, ncell, seed_offset=41)
     q, _ = _gpu_qc(plan, f)
     ref, ratio = _oracle_qc(f, op, ratios=True)
     _check_f32(q, ref, ratio)
