@@ -140,8 +140,12 @@ fks_status fks_plan_copy_tables(const fks_plan* plan, double* ab_host, double* d
  *   f      device, const, [ncell][n][n][n] FP64: the post-transport distribution f*.
  *   q_out  device, [ncell][n^3] FP64, or NULL: receives Q_c, the collision
  *          operator after the conservation projection (Section 3.2).
- *   f_out  device, [ncell][n^3] FP64, or NULL: receives f* + dt_over_tau * Q_c
- *          (eq. f_coll).  May alias f (in-place update); must not overlap q_out.
+ *   f_out  device, [ncell][n^3] FP64, or NULL: receives f_base + dt_over_tau * Q_c
+ *          (eq. f_coll).  May alias f or f_base (in-place update); must not
+ *          overlap q_out.
+ *   f_base device, [ncell][n^3] FP64, or NULL (= f): the state the update starts
+ *          from.  With f_base != f one call is a stage of a Runge-Kutta step,
+ *          e.g. the midpoint rule f + dt Q(f + dt/2 Q(f)) is two calls.
  *   At least one of q_out, f_out must be non-NULL.  ncell >= 0 (0 = nothing).
  *   f, q_out and f_out must be 16-byte aligned (every cell boundary of an
  *   array from hipMalloc is).
@@ -153,6 +157,7 @@ typedef struct {
     double*         f_out;
     int64_t         ncell;
     double          dt_over_tau;
+    const double*   f_base;
 } fks_segment;
 
 /* Device workspace bytes needed by fks_collide_batch for these segments (host call). */

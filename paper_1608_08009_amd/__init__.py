@@ -63,7 +63,7 @@ class PlanInfo(C.Structure):
 class Segment(C.Structure):
     _fields_ = [
         ("plan", C.c_void_p), ("f", C.c_void_p), ("q_out", C.c_void_p), ("f_out", C.c_void_p),
-        ("ncell", C.c_int64), ("dt_over_tau", C.c_double),
+        ("ncell", C.c_int64), ("dt_over_tau", C.c_double), ("f_base", C.c_void_p),
     ]
 
 
@@ -250,16 +250,24 @@ class Plan:
         return ab, dirs
 
 
+def _segment_fields(item):
+    """(plan, f, q_out, f_out, ncell, dt_over_tau[, f_base]) -> the seven fields."""
+    if len(item) == 6:
+        return tuple(item) + (None,)
+    return tuple(item)
+
+
 def _segments(items):
     arr = (Segment * len(items))()
-    for i, (plan, f, q_out, f_out, ncell, dt) in enumerate(items):
+    for i, item in enumerate(items):
+        plan, f, q_out, f_out, ncell, dt, f_base = _segment_fields(item)
         arr[i] = Segment(plan.handle.value if plan is not None else None, _ptr(f), _ptr(q_out),
-                         _ptr(f_out), ncell, dt)
+                         _ptr(f_out), ncell, dt, _ptr(f_base))
     return arr
 
 
 def workspace_size(segments) -> int:
-    """segments: list of (plan, f, q_out, f_out, ncell, dt_over_tau)."""
+    """segments: list of (plan, f, q_out, f_out, ncell, dt_over_tau[, f_base])."""
     arr = _segments(segments)
     out = C.c_size_t()
     _check(lib().fks_workspace_size(arr, len(segments), C.byref(out)), "fks_workspace_size")
@@ -274,11 +282,13 @@ def collide_batch(segments, workspace=None, stream=None):
     workspace tensor (reuse it).
     """
     import torch
-    for (plan, f, q_out, f_out, ncell, dt) in segments:
+    for item in segments:
+        plan, f, q_out, f_out, ncell, dt, f_base = _segment_fields(item)
         nn = ncell * plan.cell_size
         _require_device_f64(f, "f", nn)
         _require_device_f64(q_out, "q_out", nn)
         _require_device_f64(f_out, "f_out", nn)
+        _require_device_f64(f_base, "f_base", nn)
     if workspace is None:
         need = workspace_size(segments)
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
@@ -288,11 +298,12 @@ def collide_batch(segments, workspace=None, stream=None):
     return workspace
 
 
-def collide(plan: Plan, f, q_out=None, f_out=None, dt_over_tau: float = 0.0, workspace=None, stream=None):
+def collide(plan: Plan, f, q_out=None, f_out=None, dt_over_tau: float = 0.0, workspace=None, stream=None,
+            f_base=None):
     """Single-segment convenience wrapper; f is [ncell, n, n, n] (dim 3) or [ncell, n, n]
-    (dim 2) float64 on the GPU."""
+    (dim 2) float64 on the GPU.  f_out = f_base + dt_over_tau Q_c(f) (f_base defaults to f)."""
     ncell = f.numel() // plan.cell_size
-    return collide_batch([(plan, f, q_out, f_out, ncell, dt_over_tau)], workspace, stream)
+    return collide_batch([(plan, f, q_out, f_out, ncell, dt_over_tau, f_base)], workspace, stream)
 
 
 def moments(f, n: int, T: float, U=None, stream=None):

@@ -119,6 +119,7 @@ struct Args2 {
     const double* f;
     double* q_out;
     double* f_out;
+    const double* f_base;
     int64_t ncell;
     double dt;
     const void* tab;   // [J][N][N] pairs (a, b) in the transform type
@@ -236,7 +237,7 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         const double uy = -1.0 + y * h;
         const double qc = (double)q[y] - (lx + lam[2] * uy + lam[3] * fma(ux, ux, uy * uy));
         if (A.q_out) A.q_out[base + y] = qc;
-        if (A.f_out) A.f_out[base + y] = fma(A.dt, qc, A.f[base + y]);
+        if (A.f_out) A.f_out[base + y] = fma(A.dt, qc, A.f_base[base + y]);
     });
 }
 
@@ -273,6 +274,7 @@ hipError_t collide_2d(const fks_plan* p, const fks_segment& s, hipStream_t st) {
     a.f = s.f;
     a.q_out = s.q_out;
     a.f_out = s.f_out;
+    a.f_base = s.f_base ? s.f_base : s.f;
     a.ncell = s.ncell;
     a.dt = s.dt_over_tau;
     a.J = p->J;

@@ -489,8 +489,9 @@ static fks_status check_segment(const fks_segment& s) {
     if (s.ncell == 0) return FKS_OK;
     if (!s.f || (!s.q_out && !s.f_out)) return FKS_ERR_INVALID;
     if (!std::isfinite(s.dt_over_tau)) return FKS_ERR_INVALID;
-    // the kernels move f, q_out and f_out in 16-byte vectors
-    if (((uintptr_t)s.f | (uintptr_t)s.q_out | (uintptr_t)s.f_out) & 15u) return FKS_ERR_INVALID;
+    // the kernels move f, q_out, f_out and f_base in 16-byte vectors
+    if (((uintptr_t)s.f | (uintptr_t)s.q_out | (uintptr_t)s.f_out | (uintptr_t)s.f_base) & 15u)
+        return FKS_ERR_INVALID;
     size_t bytes = (size_t)s.ncell * s.plan->desc.n * s.plan->desc.n * sizeof(double);
     if (s.plan->dim == 3) bytes *= (size_t)s.plan->desc.n;
     if (s.q_out && s.f_out) {
@@ -507,6 +508,17 @@ static fks_status check_segment(const fks_segment& s) {
         const char* a = (const char*)s.f_out;
         const char* b = (const char*)s.f;
         if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+    }
+    if (s.f_base && s.f_base != s.f) {
+        const char* a = (const char*)s.f_base;
+        if (s.q_out) {
+            const char* b = (const char*)s.q_out;
+            if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+        }
+        if (s.f_out && s.f_out != s.f_base) {
+            const char* b = (const char*)s.f_out;
+            if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+        }
     }
     return FKS_OK;
 }

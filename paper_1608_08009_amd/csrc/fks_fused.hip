@@ -19,7 +19,8 @@
 //   3. store the partial Q (FP32)
 //   k_finish, per cell: Q = sum of the two partials, FP64 projection
 //      lambda = G^{-1} C Q, Q_c = Q - C^T lambda, q_out = Q_c and/or
-//      f_out = f + dt/tau Q_c (eqs. minim1, f_coll)
+//      f_out = f_base + dt/tau Q_c (eqs. minim1, f_coll; f_base = f unless a
+//      Runge-Kutta stage)
 //
 // Thread layouts (t = hi * n + lo, hi in [0, n/P), HP = n/P; pencil p in [0, P)):
 //   C: pencil (y = hi + HP p, z = lo), registers over x      (physical side)
@@ -124,6 +125,7 @@ struct FusedArgs {
     const double* f;
     double* q_out;
     double* f_out;
+    const double* f_base;   // state of the update (f unless a Runge-Kutta stage)
     int64_t ncell;
     double dt;
     const cx<float>* tab;   // [J][(n/2+1) n n] balanced (a, b)
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
     if (A.f_out) {
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            const d2v* fi = (const d2v*)(A.f + base + k * FT * VW);
+            const d2v* fi = (const d2v*)(A.f_base + base + k * FT * VW);
             d2v* o = (d2v*)(A.f_out + base + k * FT * VW);
             const d2v f0 = __builtin_nontemporal_load(fi), f1 = __builtin_nontemporal_load(fi + 1);
             __builtin_nontemporal_store(d2v{fma(A.dt, qv[k][0], f0[0]), fma(A.dt, qv[k][1], f0[1])}, o);
@@ -488,6 +490,7 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     a.f = s.f;
     a.q_out = s.q_out;
     a.f_out = s.f_out;
+    a.f_base = s.f_base ? s.f_base : s.f;
     a.ncell = s.ncell;
     a.dt = s.dt_over_tau;
     a.tab = reinterpret_cast<const cx<float>*>(p->d_tab32);

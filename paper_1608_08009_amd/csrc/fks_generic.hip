@@ -9,7 +9,7 @@
 //             z-pass with Z = (a_j + i b_j) fhat on input, y-pass,
 //             x-pass with acc += Re(z) Im(z) on output               (eq. ode, fast form)
 //   finish:   FP64 moments of acc, lambda = G^{-1} C acc, Q_c = acc - C^T lambda,
-//             outputs q_out = Q_c and/or f_out = f + dt/tau Q_c      (eqs. minim1, f_coll)
+//             outputs q_out = Q_c and/or f_out = f_base + dt/tau Q_c (eqs. minim1, f_coll)
 #include <hip/hip_runtime.h>
 
 #include "fks_common.hpp"
@@ -206,7 +206,8 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
             g_pass_y<T, N, 1><<<grid, bs, 0, st>>>(work, C);
             g_inv_x<T, N><<<grid, bs, 0, st>>>(work, acc, C, j == 0 ? 1 : 0);
         }
-        g_finish<T, N><<<C, 256, 0, st>>>(acc, f, s.q_out ? s.q_out + c0 * (int64_t)NN : nullptr,
+        const double* fb = (s.f_base ? s.f_base : s.f) + c0 * (int64_t)NN;
+        g_finish<T, N><<<C, 256, 0, st>>>(acc, fb, s.q_out ? s.q_out + c0 * (int64_t)NN : nullptr,
                                           s.f_out ? s.f_out + c0 * (int64_t)NN : nullptr, s.dt_over_tau, p->gc);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

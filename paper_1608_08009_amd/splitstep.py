@@ -4,6 +4,13 @@ One step (Section 3.1, eqs. transport/collision splitting, f_bar and f_coll):
     f*      = transport_shift(f)                      (fks_transport_shift)
     f^{n+1} = f* + (dt/tau) Q_c(f*)                   (fks_collide_batch)
 where Q_c is the fast spectral operator after the conservation projection.
+Variants (the paper names higher-order splittings and other collision
+integrators as possible; Section 3.1):
+  * scheme="strang": half a transport step, the collision step, half a
+    transport step (the transport shift is exact for any dt);
+  * collision="rk2": the midpoint rule for the collision ODE,
+    f^{n+1} = f* + (dt/tau) Q_c(f* + (dt/2tau) Q_c(f*)), as two calls of
+    fks_collide_batch (the second with f_base = f*).
 Every step runs in the HIP library; this module only sequences the calls.
 """
 from __future__ import annotations
@@ -38,25 +45,48 @@ def stable_dt(space: Space, T: float, tau: float, R: float, gamma: float, c_gamm
 
 
 class SplitStepper:
-    """Owns the ping-pong buffer, the workspace and the transport offsets of one run."""
+    """Owns the ping-pong buffers, the workspace and the transport offsets of one run."""
 
-    def __init__(self, plan: Plan, space: Space, f, bc_f=None):
+    def __init__(self, plan: Plan, space: Space, f, bc_f=None, scheme: str = "lie",
+                 collision: str = "euler"):
         import torch
+        if scheme not in ("lie", "strang") or collision not in ("euler", "rk2"):
+            raise ValueError("scheme must be 'lie' or 'strang', collision 'euler' or 'rk2'")
         self.plan = plan
         self.space = space
         self.n = plan.n
         self.T = plan.desc.T
         self.f = f
         self.tmp = torch.empty_like(f)
+        self.mid = torch.empty_like(f) if collision == "rk2" else None
         self.bc_f = bc_f
+        self.scheme = scheme
+        self.collision = collision
         self.offsets = np.zeros((3, self.n), dtype=np.float64)
         seg = [(plan, self.tmp, None, self.f, space.ncell, 0.0)]
         self.ws = torch.empty(max(workspace_size(seg), 1), dtype=torch.uint8, device=f.device)
         self.steps = 0
 
-    def step(self, dt: float, tau: float) -> None:
+    def _transport(self, src, dst, dt: float) -> None:
         sp = self.space
-        transport_shift(self.f, self.tmp, sp.nx, sp.ny, sp.nz, sp.dx, sp.bc, self.n, self.T, dt,
+        transport_shift(src, dst, sp.nx, sp.ny, sp.nz, sp.dx, sp.bc, self.n, self.T, dt,
                         self.offsets, bc_f=self.bc_f)
-        collide_batch([(self.plan, self.tmp, None, self.f, sp.ncell, dt / tau)], workspace=self.ws)
+
+    def _collide(self, src, dst, dt_over_tau: float) -> None:
+        nc = self.space.ncell
+        if self.collision == "euler":
+            collide_batch([(self.plan, src, None, dst, nc, dt_over_tau)], workspace=self.ws)
+        else:
+            collide_batch([(self.plan, src, None, self.mid, nc, 0.5 * dt_over_tau)], workspace=self.ws)
+            collide_batch([(self.plan, self.mid, None, dst, nc, dt_over_tau, src)], workspace=self.ws)
+
+    def step(self, dt: float, tau: float) -> None:
+        if self.scheme == "lie":
+            self._transport(self.f, self.tmp, dt)
+            self._collide(self.tmp, self.f, dt / tau)
+        else:
+            self._transport(self.f, self.tmp, 0.5 * dt)
+            self._collide(self.tmp, self.f, dt / tau)
+            self._transport(self.f, self.tmp, 0.5 * dt)
+            self.f, self.tmp = self.tmp, self.f
         self.steps += 1

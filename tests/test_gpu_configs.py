@@ -192,3 +192,69 @@ def test_uneven_batch_reduced(prec):
                 assert e <= 1.5e-6 * (1 + ratio[c]), (e, ratio[c])
     for p in plans:
         p.close()
+
+
+# ---------------------------------------------------------------- Runge-Kutta stages and Strang splitting
+
+@pytest.mark.parametrize("prec,tol", [(fks.PREC_F64, 1e-13), (fks.PREC_F32_FIX64, 1e-6)])
+def test_f_base_stage_and_aliasing(prec, tol):
+    # f_out = f_base + dt Q_c(f): the midpoint rule as two calls, with f_out aliasing f_base
+    n, T, ncell, dt = 16, 8.0, 5, 0.05
+    f = synth.two_maxwellian_cells(n, T, ncell, seed_offset=610)
+    op = O.make_plan(n, T)
+    Qc = lambda g: np.stack([O.conserve_Q(O.collide_fast64(c, op), n, T) for c in g])   # noqa: E731
+    ref = f + dt * Qc(f + 0.5 * dt * Qc(f))
+    with fks.Plan(fks.Desc(n=n, T=T, precision=prec)) as plan:
+        fd = _dev(f)
+        mid = torch.empty_like(fd)
+        fks.collide(plan, fd, f_out=mid, dt_over_tau=0.5 * dt)
+        fks.collide(plan, mid, f_out=fd, dt_over_tau=dt, f_base=fd)        # f_out aliases f_base
+        torch.cuda.synchronize()
+        got = fd.cpu().numpy()
+        q = torch.empty_like(fd)
+        with pytest.raises(fks.FksError) as e:
+            fks.collide(plan, mid, q_out=q, f_out=fd, dt_over_tau=dt, f_base=q)   # f_base overlaps q_out
+        assert e.value.status == fks.FKS_ERR_INVALID
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("scheme,collision", [("strang", "euler"), ("lie", "rk2"), ("strang", "rk2")])
+def test_split_step_variants_match_oracle(scheme, collision):
+    n, T, nx, tau, steps = 16, 8.0, 8, 1e-2, 3
+    f0, bc = _sod_initial(n, T, nx)
+    plan = fks.Plan(fks.Desc(n=n, T=T, precision=fks.PREC_F64))
+    space = Space(nx, 1, 1, 1.0 / nx, (fks.BC_DIRICHLET, fks.BC_PERIODIC, fks.BC_PERIODIC))
+    dt = stable_dt(space, T, tau, plan.info.R, 1.0, plan.info.c_gamma, 1.0)
+    st = SplitStepper(plan, space, _dev(f0.reshape(1, 1, nx, n, n, n)), bc_f=_dev(bc),
+                      scheme=scheme, collision=collision)
+    for _ in range(steps):
+        st.step(dt, tau)
+    torch.cuda.synchronize()
+    got = st.f.cpu().numpy().reshape(nx, n, n, n)
+    op = O.make_plan(n, T)
+    Qc = lambda c: O.conserve_Q(O.collide_fast64(c, op), n, T)   # noqa: E731
+    g = f0.reshape(1, 1, nx, n, n, n)
+    off = np.zeros((3, n))
+
+    def transport(g, h):
+        nonlocal off
+        off, s = O.transport_offsets_step(off, n, T, space.dx, h)
+        return O.transport_shift(g, s, n, bc=("dirichlet", "periodic", "periodic"), bc_f=bc)
+
+    def collide(g):
+        out = []
+        for c in g.reshape(nx, n, n, n):
+            if collision == "euler":
+                out.append(c + dt / tau * Qc(c))
+            else:
+                out.append(c + dt / tau * Qc(c + 0.5 * dt / tau * Qc(c)))
+        return np.stack(out).reshape(g.shape)
+
+    for _ in range(steps):
+        if scheme == "lie":
+            g = collide(transport(g, dt))
+        else:
+            g = transport(collide(transport(g, 0.5 * dt)), 0.5 * dt)
+    assert np.array_equal(st.offsets, off)
+    assert _rel(got, g.reshape(nx, n, n, n)) <= 1e-12
+    plan.close()

@@ -132,3 +132,31 @@ def test_test11_converges_to_the_exact_solution():
     for a, b in zip(ns, ns[1:]):
         assert errs[b][0] < errs[a][0] and errs[b][1] < errs[a][1]
     assert errs[32][0] <= 2e-3 and errs[32][1] <= 1e-3
+
+
+def test_midpoint_rule_is_second_order_and_euler_first():
+    # the collision ODE df/dt = Q_c(f) integrated by forward Euler (eq. f_coll) and by the
+    # midpoint rule, against a fine-step reference on the same grid: halving dt divides the
+    # error by about 2 (Euler) and 4 (midpoint); catches a midpoint stage with the wrong
+    # base state or step size
+    n, T, A, t_end = 16, 6.0, 8, 0.8
+    p = O2.make_plan2(n, T, A)
+    Qc = lambda g: O2.conserve2_Q(O2.collide2_fast64(g, p), n, T)   # noqa: E731
+    f0 = O2.bkw2d_initial(n, T)
+
+    def euler(dt):
+        g = f0.copy()
+        for _ in range(int(round(t_end / dt))):
+            g = g + dt * Qc(g)
+        return g
+
+    def midpoint(dt):
+        g = f0.copy()
+        for _ in range(int(round(t_end / dt))):
+            g = g + dt * Qc(g + 0.5 * dt * Qc(g))
+        return g
+
+    ref = midpoint(0.0125)
+    e = {(k, dt): np.linalg.norm(fn(dt) - ref) for k, fn in (("e", euler), ("m", midpoint)) for dt in (0.2, 0.1)}
+    assert 1.7 < e[("e", 0.2)] / e[("e", 0.1)] < 2.3
+    assert 3.4 < e[("m", 0.2)] / e[("m", 0.1)] < 4.6
