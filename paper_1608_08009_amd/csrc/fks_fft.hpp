@@ -5,7 +5,10 @@
 // registers and all permutations are free.  The recursion is a mixed-radix
 // (4, 2, 3) decimation in time; twiddle factors are exact compile-time
 // constants computed in double precision (then rounded to the working type),
-// and multiplications by 1, -1 and +-i are removed at compile time.
+// and multiplications by 1, -1 and +-i are removed at compile time.  In the
+// radix-4 combinations each nontrivial twiddle is factored as g (1 + i t) or
+// g (t + i) (Linzer-Feig), so that g folds into the butterfly's additions as
+// FMAs: 24 instead of 28 instructions per twiddled radix-4 butterfly.
 //
 //   fft<T, N, SIGN>(x):  x[k] <- sum_n x[n] exp(SIGN * 2 pi i n k / N)   (unnormalised)
 #pragma once
@@ -117,6 +120,30 @@ FKS_HD cx<T> twiddle(cx<T> a) {
     }
 }
 
+// Twiddle factored as W = g (1 + i t) or g (t + i) with |t| <= 1 and the larger of
+// |cos|, |sin| as g (Linzer-Feig): W a = g v with v = pre(a) costing two FMAs,
+// and the radix-4 butterfly absorbs g into its additions as FMAs.
+template <typename T, int SIGN, int N, int E>
+struct ScaledTwiddle {
+    static constexpr int e = ((E % N) + N) % N;
+    static constexpr bool trivial = e == 0 || 2 * e == N || 4 * e == N || 4 * e == 3 * N;
+    static constexpr ct::sc w = ct::sincos2pi(e, N);
+    static constexpr double c = w.c;
+    static constexpr double s = SIGN > 0 ? w.s : -w.s;
+    static constexpr bool cos_major = (c < 0 ? -c : c) >= (s < 0 ? -s : s);
+    static constexpr T g = trivial ? T(1) : T(cos_major ? c : s);
+    static constexpr T t = trivial ? T(0) : T(cos_major ? s / c : c / s);
+    FKS_HD static cx<T> pre(cx<T> a) {
+        if constexpr (trivial) {
+            return twiddle<T, SIGN, N, E>(a);
+        } else if constexpr (cos_major) {   // W a = c ((x - t y) + i (y + t x))
+            return {a.x - t * a.y, a.y + t * a.x};
+        } else {                            // W a = s ((t x - y) + i (x + t y))
+            return {t * a.x - a.y, a.x + t * a.y};
+        }
+    }
+};
+
 template <int N>
 constexpr int first_radix() {
     return (N % 4 == 0) ? 4 : (N % 2 == 0 ? 2 : (N % 3 == 0 ? 3 : N));
@@ -167,16 +194,46 @@ FKS_HD void fft_rec(const cx<T> (&x)[LEN], cx<T>* y) {
         });
         sfor<M>([&](auto kI) {
             constexpr int k = decltype(kI)::value;
-            cx<T> u[R];
-            sfor<R>([&](auto rI) {
-                constexpr int r = decltype(rI)::value;
-                u[r] = twiddle<T, SIGN, N, r * k>(sub[r][k]);
-            });
-            butterfly<T, R, SIGN>(u);
-            sfor<R>([&](auto qI) {
-                constexpr int q = decltype(qI)::value;
-                y[k + M * q] = u[q];
-            });
+            if constexpr (R == 4 && !(ScaledTwiddle<T, SIGN, N, k>::trivial &&
+                                      ScaledTwiddle<T, SIGN, N, 2 * k>::trivial &&
+                                      ScaledTwiddle<T, SIGN, N, 3 * k>::trivial)) {
+                using W1 = ScaledTwiddle<T, SIGN, N, k>;
+                using W2 = ScaledTwiddle<T, SIGN, N, 2 * k>;
+                using W3 = ScaledTwiddle<T, SIGN, N, 3 * k>;
+                const cx<T> u0 = sub[0][k];
+                const cx<T> v1 = W1::pre(sub[1][k]), v2 = W2::pre(sub[2][k]), v3 = W3::pre(sub[3][k]);
+                constexpr T g1 = W1::g, g2 = W2::g, g3 = W3::g;
+                const cx<T> a = {u0.x + g2 * v2.x, u0.y + g2 * v2.y};
+                const cx<T> b = {u0.x - g2 * v2.x, u0.y - g2 * v2.y};
+                cx<T> c, d;
+                if constexpr (g1 == g3) {         // c = g (v1 + v3), d = g (v1 - v3)
+                    const cx<T> sp = cadd(v1, v3), sm = csub(v1, v3);
+                    const cx<T> dm = cmul_i<T, SIGN>(sm);
+                    y[k] = {a.x + g1 * sp.x, a.y + g1 * sp.y};
+                    y[k + 2 * M] = {a.x - g1 * sp.x, a.y - g1 * sp.y};
+                    y[k + M] = {b.x + g1 * dm.x, b.y + g1 * dm.y};
+                    y[k + 3 * M] = {b.x - g1 * dm.x, b.y - g1 * dm.y};
+                } else {
+                    const cx<T> t3 = {g3 * v3.x, g3 * v3.y};
+                    c = {g1 * v1.x + t3.x, g1 * v1.y + t3.y};
+                    d = cmul_i<T, SIGN>(cx<T>{g1 * v1.x - t3.x, g1 * v1.y - t3.y});
+                    y[k] = cadd(a, c);
+                    y[k + 2 * M] = csub(a, c);
+                    y[k + M] = cadd(b, d);
+                    y[k + 3 * M] = csub(b, d);
+                }
+            } else {
+                cx<T> u[R];
+                sfor<R>([&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    u[r] = twiddle<T, SIGN, N, r * k>(sub[r][k]);
+                });
+                butterfly<T, R, SIGN>(u);
+                sfor<R>([&](auto qI) {
+                    constexpr int q = decltype(qI)::value;
+                    y[k + M * q] = u[q];
+                });
+            }
         });
     }
 }
