@@ -236,6 +236,27 @@ fks_status fks_profile_last(double* kernel_ms, int32_t capacity, int32_t* count)
 const char* fks_status_string(fks_status status);
 
 /*
+ * Spectrum of a batch of cells (Section 3.3, eq. FC on the grid), in FP64: the
+ * optional forward transform of Q (or of f) for a spectral-space update.
+ *   xhat_k = n^-3 sum_j x_j exp(-i kappa k.v_j),  kappa = pi/T,  v_j = -T + j dv,
+ * which does not depend on T: exp(-i kappa k.v_j) = (-1)^k exp(-2 pi i k.j / n).
+ *   x      device, const, [ncell][n][n][n] FP64 (x-major, as f)
+ *   xhat   device, [ncell][n][n][n/2+1][2] FP64: (re, im) at (kx, ky, kz), kx and
+ *          ky in FFT storage order (0..n/2-1, -n/2..-1), kz in [0, n/2]; the rest
+ *          of the spectrum is xhat(-k) = conj xhat(k).
+ *   zero_nyquist  1: every mode with a component equal to n/2 is set to 0 (what
+ *          the collision operator uses); 0: the plain transform.
+ *   workspace  device, 256-byte aligned, at least one cell (16 n^3 bytes); cells
+ *          are processed in chunks of up to min(512, ws_bytes / (16 n^3)).
+ *          fks_spectrum_workspace_size gives the size for the largest chunk.
+ * n as for fks_plan_desc (dim 3).  No overlap between x, xhat and workspace.
+ * Errors: FKS_ERR_INVALID, FKS_ERR_UNSUPPORTED (n), FKS_ERR_DEVICE.
+ */
+fks_status fks_spectrum_workspace_size(int64_t ncell, int32_t n, size_t* bytes);
+fks_status fks_spectrum(const double* x, double* xhat, int64_t ncell, int32_t n, int32_t zero_nyquist,
+                        void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
  * BGK relaxation operator with the conservative discrete Maxwellian
  * (Section 2 eq. ibgk; Section 3.2 eq. minimMax), FP64, per cell:
  *   U = C f;  (rho, u, theta) with d_v rho theta = sum |v|^2 f dv^d - rho |u|^2;

@@ -38,7 +38,7 @@ EXPORTED = [
     "fks_workspace_size", "fks_collide_batch", "fks_moments", "fks_conserve",
     "fks_transport_shift", "fks_status_string", "fks_desc_validate",
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
-    "fks_host_tables_2d", "fks_bgk",
+    "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
 ]
 
 
@@ -111,6 +111,8 @@ def lib() -> C.CDLL:
     L.fks_profile_last.argtypes = [vp, i32, C.POINTER(i32)]
     L.fks_host_tables_2d.argtypes = [C.POINTER(PlanDesc), C.POINTER(i32), vp]
     L.fks_bgk.argtypes = [C.POINTER(BgkDesc), vp, vp, vp, i64, dbl, vp]
+    L.fks_spectrum_workspace_size.argtypes = [i64, i32, C.POINTER(sz)]
+    L.fks_spectrum.argtypes = [vp, vp, i64, i32, i32, vp, sz, vp]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -366,6 +368,27 @@ def bgk_validate(dim: int, n: int, T: float, nu: float, nu_rho: int = 0, step: i
     """Status of fks_bgk on an empty batch (argument validation only, no device work)."""
     d = BgkDesc(dim, n, T, nu, nu_rho, step)
     return lib().fks_bgk(C.byref(d), None, None, None, 0, dt_over_tau, None)
+
+
+def spectrum(x, n: int, xhat=None, zero_nyquist: bool = False, workspace=None, stream=None):
+    """xhat[ncell, n, n, n/2+1] complex128 = n^-3 sum_j x_j exp(-i kappa k.v_j) (fks_spectrum);
+    x is [ncell, n, n, n] float64 on the GPU."""
+    import torch
+    ncell = x.numel() // n ** 3
+    _require_device_f64(x, "x", ncell * n ** 3)
+    if xhat is None:
+        xhat = torch.empty((ncell, n, n, n // 2 + 1), dtype=torch.complex128, device=x.device)
+    if not (isinstance(xhat, torch.Tensor) and xhat.is_cuda and xhat.dtype == torch.complex128
+            and xhat.is_contiguous() and xhat.numel() == ncell * n * n * (n // 2 + 1)):
+        raise ValueError("xhat must be a contiguous complex128 GPU tensor of ncell*n*n*(n/2+1) elements")
+    if workspace is None:
+        need = C.c_size_t()
+        _check(lib().fks_spectrum_workspace_size(ncell, n, C.byref(need)), "fks_spectrum_workspace_size")
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=x.device)
+    _check(lib().fks_spectrum(C.c_void_p(_ptr(x)), C.c_void_p(_ptr(xhat)), ncell, n, 1 if zero_nyquist else 0,
+                              C.c_void_p(_ptr(workspace)), workspace.numel(), C.c_void_p(_stream_ptr(stream))),
+           "fks_spectrum")
+    return xhat
 
 
 def profile_enable(on: bool = True) -> None:

@@ -576,6 +576,33 @@ fks_status fks_conserve(double* f, const double* U, int64_t ncell, int32_t n, do
     return conserve(f, U, ncell, n, T, (hipStream_t)hip_stream) == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
 }
 
+fks_status fks_spectrum_workspace_size(int64_t ncell, int32_t n, size_t* bytes) {
+    if (!bytes || ncell < 0 || !supported_n(n)) return !bytes || ncell < 0 ? FKS_ERR_INVALID : FKS_ERR_UNSUPPORTED;
+    *bytes = ncell == 0 ? 0 : spectrum_workspace_bytes(n, ncell);
+    return FKS_OK;
+}
+
+fks_status fks_spectrum(const double* x, double* xhat, int64_t ncell, int32_t n, int32_t zero_nyquist,
+                        void* workspace, size_t ws_bytes, void* hip_stream) {
+    if (ncell < 0 || (zero_nyquist != 0 && zero_nyquist != 1)) return FKS_ERR_INVALID;
+    if (!supported_n(n)) return n > 0 ? FKS_ERR_UNSUPPORTED : FKS_ERR_INVALID;
+    if (ncell == 0) return FKS_OK;
+    if (!x || !xhat || !workspace || ((uintptr_t)workspace & 255u)) return FKS_ERR_INVALID;
+    const size_t one = (size_t)n * n * n * 16;   // one cell of complex FP64 work
+    if (ws_bytes < one) return FKS_ERR_INVALID;
+    const size_t in_bytes = (size_t)ncell * n * n * n * sizeof(double);
+    const size_t out_bytes = (size_t)ncell * n * n * (n / 2 + 1) * 2 * sizeof(double);
+    const char* a = (const char*)x;
+    const char* b = (const char*)xhat;
+    const char* w = (const char*)workspace;
+    if ((a < b + out_bytes && b < a + in_bytes) || (w < b + out_bytes && b < w + ws_bytes) ||
+        (w < a + in_bytes && a < w + ws_bytes))
+        return FKS_ERR_INVALID;
+    return spectrum(x, xhat, ncell, n, zero_nyquist, workspace, ws_bytes, (hipStream_t)hip_stream) == hipSuccess
+               ? FKS_OK
+               : FKS_ERR_DEVICE;
+}
+
 fks_status fks_bgk(const fks_bgk_desc* d, const double* f, double* q_out, double* f_out, int64_t ncell,
                    double dt_over_tau, void* hip_stream) {
     if (!d || ncell < 0 || !std::isfinite(dt_over_tau)) return FKS_ERR_INVALID;

@@ -181,6 +181,55 @@ __global__ __launch_bounds__(256) void g_finish(const T* __restrict__ acc, const
     }
 }
 
+// Spectrum output pass: z transform of the y-passed work array, then
+// xhat[c][kx][ky][kz] = (-1)^(kx+ky+kz) n^-3 DFT (eq. FC with v_j = -T + j dv:
+// exp(-i kappa k.v_j) = (-1)^k exp(-2 pi i k j / n)), kz in [0, n/2], FP64.
+template <int N>
+__global__ __launch_bounds__(128) void g_spec_z(const cx<double>* __restrict__ work, double* __restrict__ xhat,
+                                                int C, int zero_nyquist) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
+    const cx<double>* p = work + (size_t)c * N * N * N + (kx * N + ky) * N;
+    cx<double> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int z = decltype(I)::value;
+        v[z] = p[z];
+    });
+    fft<double, N, -1>(v);
+    constexpr int HZ = N / 2 + 1;
+    const double s = ((kx + ky) & 1 ? -1.0 : 1.0) / ((double)N * N * N);
+    const bool nyq_xy = zero_nyquist && (kx == N / 2 || ky == N / 2);
+    double* o = xhat + 2 * ((size_t)c * N * N * HZ + (size_t)(kx * N + ky) * HZ);
+    sfor<HZ>([&](auto I) {
+        constexpr int kz = decltype(I)::value;
+        const double sk = (nyq_xy || (zero_nyquist && kz == N / 2)) ? 0.0 : ((kz & 1) ? -s : s);
+        o[2 * kz] = v[kz].x * sk;
+        o[2 * kz + 1] = v[kz].y * sk;
+    });
+}
+
+template <int N>
+hipError_t run_spectrum(const double* x, double* xhat, int64_t ncell, int zero_nyquist, void* ws, size_t ws_bytes,
+                        hipStream_t st) {
+    constexpr size_t NN = (size_t)N * N * N;
+    const int64_t fit = (int64_t)(ws_bytes / (NN * sizeof(cx<double>)));
+    const int chunk = (int)std::min<int64_t>(std::min<int64_t>(ncell, kChunk), fit);
+    if (chunk < 1) return hipErrorInvalidValue;
+    cx<double>* work = (cx<double>*)ws;
+    const int bs = 128;
+    for (int64_t c0 = 0; c0 < ncell; c0 += chunk) {
+        const int C = (int)std::min<int64_t>(chunk, ncell - c0);
+        const unsigned grid = (unsigned)((C * N * N + bs - 1) / bs);
+        g_fwd_x<double, N><<<grid, bs, 0, st>>>(x + c0 * (int64_t)NN, work, C);
+        g_pass_y<double, N, -1><<<grid, bs, 0, st>>>(work, C);
+        g_spec_z<N><<<grid, bs, 0, st>>>(work, xhat + 2 * c0 * (int64_t)(N * N * (N / 2 + 1)), C, zero_nyquist);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 template <typename T, int N>
@@ -241,6 +290,26 @@ size_t generic_workspace_bytes(const fks_plan* p, int64_t ncell) {
                align256(chunk * NN * sizeof(double));
     return align256(chunk * H * sizeof(cx<float>)) + align256(chunk * NN * sizeof(cx<float>)) +
            align256(chunk * NN * sizeof(float));
+}
+
+size_t spectrum_workspace_bytes(int n, int64_t ncell) {
+    const size_t chunk = (size_t)std::min<int64_t>(std::max<int64_t>(ncell, 1), kChunk);
+    return chunk * (size_t)n * n * n * sizeof(cx<double>);
+}
+
+hipError_t spectrum(const double* x, double* xhat, int64_t ncell, int n, int zero_nyquist, void* ws, size_t ws_bytes,
+                    hipStream_t st) {
+    switch (n) {
+        case 4: return run_spectrum<4>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 6: return run_spectrum<6>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 8: return run_spectrum<8>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 12: return run_spectrum<12>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 16: return run_spectrum<16>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 24: return run_spectrum<24>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 32: return run_spectrum<32>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        case 48: return run_spectrum<48>(x, xhat, ncell, zero_nyquist, ws, ws_bytes, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t collide_generic(const fks_plan* p, const fks_segment& s, void* ws, size_t ws_bytes, hipStream_t st) {

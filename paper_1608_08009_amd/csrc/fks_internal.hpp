@@ -71,6 +71,11 @@ size_t generic_workspace_bytes(const fks_plan* plan, int64_t ncell);
 hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
                            hipStream_t stream);
 
+// spectrum of a batch (multi-pass FP64, fks_generic.hip)
+size_t spectrum_workspace_bytes(int n, int64_t ncell);
+hipError_t spectrum(const double* x, double* xhat, int64_t ncell, int n, int zero_nyquist, void* ws, size_t ws_bytes,
+                    hipStream_t st);
+
 // optional event timing of the fused path (fks_fused.hip)
 void profile_enable(bool on);
 hipError_t profile_last(double* ms, int cap, int* count);

@@ -1,5 +1,6 @@
 """Host-side checks of libfks.so that need no GPU: loading, exported symbols,
 descriptor validation, and the FP64 host precompute against the oracle."""
+import ctypes as C
 import math
 import os
 import re
@@ -137,3 +138,14 @@ def test_bgk_validation(kw, expect):
     args = dict(dim=3, n=32, T=8.0, nu=1.0)
     args.update(kw)
     assert fks.bgk_validate(**args) == expect
+
+
+def test_spectrum_workspace_size_host():
+    b = C.c_size_t()
+    assert fks.lib().fks_spectrum_workspace_size(7, 32, C.byref(b)) == fks.FKS_OK
+    assert b.value == 7 * 32 ** 3 * 16
+    assert fks.lib().fks_spectrum_workspace_size(10_000, 16, C.byref(b)) == fks.FKS_OK
+    assert b.value == 512 * 16 ** 3 * 16
+    assert fks.lib().fks_spectrum_workspace_size(1, 10, C.byref(b)) == fks.FKS_ERR_UNSUPPORTED
+    assert fks.lib().fks_spectrum(None, None, 0, 16, 0, None, 0, None) == fks.FKS_OK      # empty batch
+    assert fks.lib().fks_spectrum(None, None, 1, 16, 2, None, 0, None) == fks.FKS_ERR_INVALID

@@ -330,3 +330,31 @@ def test_transport_matches_oracle(bc):
     torch.cuda.synchronize()
     assert np.array_equal(off, off_or)
     assert np.array_equal(fa.cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------- spectrum (forward transform of Q or f)
+
+@pytest.mark.parametrize("n,ncell,ws_cells,zn", [(8, 7, 3, False), (12, 5, 5, True), (32, 3, 2, False),
+                                                (48, 2, 2, True)])
+def test_spectrum_matches_oracle(n, ncell, ws_cells, zn):
+    # eq. FC on the grid, against the oracle's transform; a workspace of ws_cells cells forces chunking
+    f = synth.two_maxwellian_cells(n, T_BOX, ncell, seed_offset=700 + n)
+    ws = torch.empty(ws_cells * n ** 3 * 16, dtype=torch.uint8, device="cuda")
+    got = fks.spectrum(_dev(f), n, zero_nyquist=zn, workspace=ws).cpu().numpy()
+    ref = O.spectrum(f, n, T_BOX, zero_nyquist=zn)[..., : n // 2 + 1]
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+def test_spectrum_of_the_collision_operator_conserves_mass():
+    # the optional forward transform of Q: Qhat_c(0) = mass of Q_c / (2T)^3 = 0
+    n, ncell = 16, 4
+    plan = _plan(n=n, T=T_BOX, precision=fks.PREC_F64)
+    f = synth.two_maxwellian_cells(n, T_BOX, ncell, seed_offset=71)
+    q, _ = _gpu_qc(plan, f)
+    qh = fks.spectrum(_dev(q), n).cpu().numpy()
+    ref = O.spectrum(q, n, T_BOX, zero_nyquist=False)[..., : n // 2 + 1]
+    assert np.max(np.abs(qh - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert np.all(np.abs(qh[:, 0, 0, 0]) <= 1e-15 * np.max(np.abs(qh)))
+    with pytest.raises(fks.FksError) as e:
+        fks.spectrum(_dev(q), n, workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == fks.FKS_ERR_INVALID
