@@ -40,7 +40,7 @@ typedef enum {
     FKS_ERR_UNSUPPORTED = -2,  /* valid request outside the implemented set (e.g. odd n) */
     FKS_ERR_NOMEM = -3,        /* device allocation failed (plan creation only) */
     FKS_ERR_DEVICE = -4,       /* a HIP runtime call or kernel launch failed */
-    FKS_ERR_NUMERIC = -5       /* reserved: non-finite data detected */
+    FKS_ERR_NUMERIC = -5       /* non-finite Q_c recorded by the numeric guard (fks_numeric_status) */
 } fks_status;
 
 typedef enum {
@@ -55,6 +55,7 @@ typedef enum {
 
 /* Path selection flags (fks_plan_desc.flags). */
 #define FKS_FLAG_FORCE_GENERIC 0x1u  /* use the multi-pass path even where the fused kernel exists */
+#define FKS_FLAG_NUMERIC_GUARD 0x2u  /* record the first cell whose Q_c is not finite (fks_numeric_status) */
 
 /*
  * Operator description (Section 3.3).  Zero / non-positive optional fields
@@ -122,6 +123,18 @@ fks_status fks_plan_destroy(fks_plan* plan);
 
 /* Fills *info (host).  FKS_ERR_INVALID on NULL. */
 fks_status fks_plan_query(const fks_plan* plan, fks_plan_info* info);
+
+/*
+ * Numeric guard of a plan created with FKS_FLAG_NUMERIC_GUARD: every segment of
+ * the plan in fks_collide_batch records, in a device word the plan owns, the
+ * smallest cell index (within its segment) whose Q_c has a non-finite moment sum.
+ * This call synchronises the device, then returns FKS_ERR_NUMERIC with
+ * *first_bad_cell = that index if one was recorded since the last reset, else
+ * FKS_OK with *first_bad_cell = -1; reset = 1 clears the word afterwards.  Calls
+ * that overlap on one plan share the word.  FKS_ERR_INVALID for NULL arguments
+ * or a plan without the flag.
+ */
+fks_status fks_numeric_status(const fks_plan* plan, int64_t* first_bad_cell, int32_t reset);
 
 /*
  * Copies the plan's FP64 tables to host memory, for inspection and tests.

@@ -28,6 +28,7 @@ PREC_F32_FIX64 = 1
 RULE_GAUSS = 0
 RULE_MIDPOINT = 1
 FLAG_FORCE_GENERIC = 0x1
+FLAG_NUMERIC_GUARD = 0x2
 BGK_EULER = 0
 BGK_EXACT = 1
 BC_PERIODIC = 0
@@ -39,6 +40,7 @@ EXPORTED = [
     "fks_transport_shift", "fks_status_string", "fks_desc_validate",
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
     "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
+    "fks_numeric_status",
 ]
 
 
@@ -113,6 +115,7 @@ def lib() -> C.CDLL:
     L.fks_bgk.argtypes = [C.POINTER(BgkDesc), vp, vp, vp, i64, dbl, vp]
     L.fks_spectrum_workspace_size.argtypes = [i64, i32, C.POINTER(sz)]
     L.fks_spectrum.argtypes = [vp, vp, i64, i32, i32, vp, sz, vp]
+    L.fks_numeric_status.argtypes = [vp, C.POINTER(i64), i32]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -238,6 +241,15 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def numeric_status(self, reset: bool = True) -> int:
+        """First cell (within its segment) whose Q_c was not finite since the last reset,
+        or -1 (plans created with FLAG_NUMERIC_GUARD; synchronises the device)."""
+        cell = C.c_int64(-1)
+        st = lib().fks_numeric_status(self.handle, C.byref(cell), 1 if reset else 0)
+        if st not in (FKS_OK, FKS_ERR_NUMERIC):
+            _check(st, "fks_numeric_status")
+        return int(cell.value)
 
     def tables(self):
         """(ab FP64 numpy, dirs [M, 4]) copied from the device; ab is [J, n/2+1, n, n, 2]

@@ -125,6 +125,7 @@ struct Args2 {
     const void* tab;   // [J][N][N] pairs (a, b) in the transform type
     int J;
     const GridConst2* gc;
+    unsigned long long* guard;   // numeric guard word, or null
 };
 
 template <typename R, int N>
@@ -230,6 +231,7 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         lam[a] = v;
     }
     if (!live) return;
+    if (A.guard && i == 0 && !isfinite(s[0] + s[1] + s[2] + s[3])) atomicMin(A.guard, (unsigned long long)cell);
     const int64_t base = cell * (int64_t)NN + i * N;
     const double lx = fma(lam[1], ux, lam[0]);
     sfor<N>([&](auto yI) {
@@ -279,6 +281,7 @@ hipError_t collide_2d(const fks_plan* p, const fks_segment& s, hipStream_t st) {
     a.dt = s.dt_over_tau;
     a.J = p->J;
     a.gc = p->d_gc2;
+    a.guard = p->d_guard;
     if (p->desc.precision == FKS_PREC_F64) {
         a.tab = p->d_tab64;
         return dispatch2d<double>(p->desc.n, a, st);

@@ -238,7 +238,7 @@ static fks_status resolve_desc(const fks_plan_desc* in, fks_plan_desc* out) {
     if (d.rule != FKS_RULE_GAUSS && d.rule != FKS_RULE_MIDPOINT) return FKS_ERR_INVALID;
     if (d.precision != FKS_PREC_F64 && d.precision != FKS_PREC_F32_FIX64) return FKS_ERR_INVALID;
     if (d.radial_terms < 0 || d.radial_terms > 200) return FKS_ERR_INVALID;
-    if ((d.flags & ~FKS_FLAG_FORCE_GENERIC) != 0) return FKS_ERR_INVALID;
+    if ((d.flags & ~(FKS_FLAG_FORCE_GENERIC | FKS_FLAG_NUMERIC_GUARD)) != 0) return FKS_ERR_INVALID;
     if (d.n <= 0) return FKS_ERR_INVALID;
     if (d.dim == 0) d.dim = 3;
     if (d.dim != 2 && d.dim != 3) return FKS_ERR_INVALID;
@@ -369,6 +369,7 @@ static fks_status plan_create_2d(fks_plan* p) {
 }
 
 static void plan_free(fks_plan* p) {
+    if (p->d_guard) (void)hipFree(p->d_guard);
     if (p->d_tab64) (void)hipFree(p->d_tab64);
     if (p->d_tab32) (void)hipFree(p->d_tab32);
     if (p->d_gc) (void)hipFree(p->d_gc);
@@ -387,6 +388,17 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
     p->desc = d;
     const int n = d.n;
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FKS_ERR_DEVICE; }
+    if (d.flags & FKS_FLAG_NUMERIC_GUARD) {
+        const unsigned long long none = ~0ull;
+        if (hipMalloc(&p->d_guard, sizeof(none)) != hipSuccess) {
+            delete p;
+            return FKS_ERR_NOMEM;
+        }
+        if (hipMemcpy(p->d_guard, &none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess) {
+            plan_free(p);
+            return FKS_ERR_DEVICE;
+        }
+    }
     if (d.dim == 2) {
         st = plan_create_2d(p);
         if (st != FKS_OK) {
@@ -415,22 +427,18 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
     p->flops_per_cell = (2.0 * p->M * p->K + 2.0) * 2.5 * nn * std::log2(nn) + 7.0 * p->M * p->K * nn + 3.0 * nn;
     size_t tab_elems = (size_t)p->J * p->H * 2;
     if (hipMalloc(&p->d_tab64, tab_elems * sizeof(double)) != hipSuccess) {
-        delete p;
+        plan_free(p);
         return FKS_ERR_NOMEM;
     }
     p->table_bytes = tab_elems * sizeof(double);
     if (hipMalloc(&p->d_gc, sizeof(GridConst)) != hipSuccess ||
         hipMemcpy(p->d_gc, &p->gc, sizeof(GridConst), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(p->d_tab64);
-        if (p->d_gc) (void)hipFree(p->d_gc);
-        delete p;
+        plan_free(p);
         return FKS_ERR_NOMEM;
     }
     if (d.precision == FKS_PREC_F32_FIX64) {
         if (hipMalloc(&p->d_tab32, tab_elems * sizeof(float)) != hipSuccess) {
-            (void)hipFree(p->d_tab64);
-            (void)hipFree(p->d_gc);
-            delete p;
+            plan_free(p);
             return FKS_ERR_NOMEM;
         }
         p->table_bytes += tab_elems * sizeof(float);
@@ -439,10 +447,7 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
     }
     hipStream_t s = (hipStream_t)hip_stream;
     if (build_tables(p, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-        (void)hipFree(p->d_tab64);
-        (void)hipFree(p->d_gc);
-        if (p->d_tab32) (void)hipFree(p->d_tab32);
-        delete p;
+        plan_free(p);
         return FKS_ERR_DEVICE;
     }
     *out = p;
@@ -471,6 +476,20 @@ fks_status fks_plan_query(const fks_plan* p, fks_plan_info* info) {
     info->flops_per_cell = p->flops_per_cell;
     info->dim = p->dim;
     return FKS_OK;
+}
+
+fks_status fks_numeric_status(const fks_plan* p, int64_t* first_bad_cell, int32_t reset) {
+    if (!p || !first_bad_cell || !p->d_guard) return FKS_ERR_INVALID;
+    unsigned long long v = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&v, p->d_guard, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+        return FKS_ERR_DEVICE;
+    if (reset) {
+        const unsigned long long none = ~0ull;
+        if (hipMemcpy(p->d_guard, &none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess) return FKS_ERR_DEVICE;
+    }
+    *first_bad_cell = v == ~0ull ? -1 : (int64_t)v;
+    return v == ~0ull ? FKS_OK : FKS_ERR_NUMERIC;
 }
 
 fks_status fks_plan_copy_tables(const fks_plan* p, double* ab_host, double* dirs_host) {

@@ -134,6 +134,7 @@ struct FusedArgs {
     cx<float>* fh;          // [ncell][n/2][n][n]
     float* part;            // [ncell][2][n^3]
     const GridConst* gc;
+    unsigned long long* guard;   // numeric guard word, or null
 };
 
 template <int N>
@@ -390,6 +391,7 @@ __global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
         }
     }
     block_sum5<FT>(m, red);
+    if (A.guard && t == 0 && !isfinite(m[0] + m[1] + m[2] + m[3] + m[4])) atomicMin(A.guard, (unsigned long long)cell);
     double lam[5];
     solve5(*A.gc, m, lam);
     const int64_t base = cell * (int64_t)N3 + VW * t;
@@ -499,6 +501,7 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     a.fh = reinterpret_cast<cx<float>*>(base + w.fh);
     a.part = reinterpret_cast<float*>(base + w.part);
     a.gc = p->d_gc;
+    a.guard = p->d_guard;
     hipError_t e = prof_mark(0, st);
     if (e != hipSuccess) return e;
     k_terms<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);

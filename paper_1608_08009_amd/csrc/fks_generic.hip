@@ -148,7 +148,7 @@ __global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work, T
 template <typename T, int N>
 __global__ __launch_bounds__(256) void g_finish(const T* __restrict__ acc, const double* f,
                                                 double* __restrict__ q_out, double* f_out, double dt,
-                                                GridConst gc) {
+                                                GridConst gc, unsigned long long* guard, int64_t c0) {
     __shared__ double red[5 * 4];
     __shared__ double lam_s[5];
     const int c = blockIdx.x;
@@ -164,6 +164,7 @@ __global__ __launch_bounds__(256) void g_finish(const T* __restrict__ acc, const
     }
     block_sum5<256>(m, red);
     if (threadIdx.x == 0) {
+        if (guard && !isfinite(m[0] + m[1] + m[2] + m[3] + m[4])) atomicMin(guard, (unsigned long long)(c0 + c));
         double lam[5];
         solve5(gc, m, lam);
         for (int a = 0; a < 5; ++a) lam_s[a] = lam[a];
@@ -257,7 +258,8 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
         }
         const double* fb = (s.f_base ? s.f_base : s.f) + c0 * (int64_t)NN;
         g_finish<T, N><<<C, 256, 0, st>>>(acc, fb, s.q_out ? s.q_out + c0 * (int64_t)NN : nullptr,
-                                          s.f_out ? s.f_out + c0 * (int64_t)NN : nullptr, s.dt_over_tau, p->gc);
+                                          s.f_out ? s.f_out + c0 * (int64_t)NN : nullptr, s.dt_over_tau, p->gc,
+                                          p->d_guard, c0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -47,6 +47,7 @@ struct fks_plan {
     float* d_tab32 = nullptr;       // same, rounded to FP32 (FP32 plans only)
     fks::GridConst* d_gc = nullptr; // device copy of gc
     int dim = 3;                    // velocity dimension
+    unsigned long long* d_guard = nullptr;   // first non-finite cell (numeric guard), ~0 = none
     fks::GridConst2* d_gc2 = nullptr;   // device grid constants of a dim = 2 plan
     size_t table_bytes = 0;
     bool fused = false;             // fks_collide_batch uses the fused kernel

@@ -48,6 +48,21 @@ def test_desc_validation_rejects(field, value, expect):
     assert fks.desc_validate(d) == expect
 
 
+def test_desc_validation_accepts_the_numeric_guard_flag():
+    for flags in (fks.FLAG_NUMERIC_GUARD, fks.FLAG_NUMERIC_GUARD | fks.FLAG_FORCE_GENERIC):
+        assert fks.desc_validate(fks.Desc(n=16, T=8.0, flags=flags)) == fks.FKS_OK
+    d2 = fks.desc2d(16, 6.0)
+    d2.flags = fks.FLAG_NUMERIC_GUARD
+    assert fks.desc_validate(d2) == fks.FKS_OK
+    assert fks.desc_validate(fks.Desc(n=16, T=8.0, flags=0x4)) == fks.FKS_ERR_INVALID
+
+
+def test_numeric_status_rejects_null_plan():
+    cell = C.c_int64(7)
+    assert fks.lib().fks_numeric_status(None, C.byref(cell), 0) == fks.FKS_ERR_INVALID
+    assert cell.value == 7
+
+
 @pytest.mark.parametrize("n", [4, 6, 8, 12, 16, 24, 32, 48])
 def test_desc_validation_accepts_supported_sizes(n):
     assert fks.desc_validate(fks.Desc(n=n, T=8.0, gamma=0.5)) == fks.FKS_OK
