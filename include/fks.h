@@ -104,6 +104,7 @@ typedef struct {
     size_t  table_bytes;       /* device bytes held by the plan */
     double  flops_per_cell;    /* algorithmic flop count of one Q evaluation (see design notes) */
     int32_t dim;               /* velocity dimension (2 or 3) */
+    int32_t fused_grid;        /* workgroups the fused kernel keeps resident (0 if not fused) */
 } fks_plan_info;
 
 /*
@@ -236,7 +237,8 @@ fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_spac
 /*
  * Per-kernel timing of fks_collide_batch, for measurement tools.  While
  * enabled, the library records HIP events on the call's stream around each
- * kernel of the fused path (terms kernel, then finish kernel).
+ * kernel of the fused path: one kernel when a workgroup takes whole cells
+ * (large batches), else the terms kernel, then the finish kernel.
  * fks_profile_last waits for the last recorded call to finish and writes up
  * to `capacity` durations in milliseconds (host array), in launch order;
  * *count receives how many kernels the last call timed (0 if none).

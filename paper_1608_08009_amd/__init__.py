@@ -58,7 +58,7 @@ class PlanInfo(C.Structure):
         ("n", C.c_int32), ("M", C.c_int32), ("K", C.c_int32), ("J", C.c_int32),
         ("R", C.c_double), ("c_gamma", C.c_double), ("precision", C.c_int32),
         ("fused", C.c_int32), ("table_bytes", C.c_size_t), ("flops_per_cell", C.c_double),
-        ("dim", C.c_int32),
+        ("dim", C.c_int32), ("fused_grid", C.c_int32),
     ]
 
 

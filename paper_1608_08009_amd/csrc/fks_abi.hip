@@ -475,6 +475,7 @@ fks_status fks_plan_query(const fks_plan* p, fks_plan_info* info) {
     info->table_bytes = p->table_bytes;
     info->flops_per_cell = p->flops_per_cell;
     info->dim = p->dim;
+    info->fused_grid = p->fused ? p->fused_grid : 0;
     return FKS_OK;
 }
 

@@ -1,6 +1,13 @@
-// Fused FP32 collision kernel with FP64 conservation fix (one launch per batch).
+// Fused FP32 collision kernel with FP64 conservation fix.
 //
-// Work decomposition: two workgroups on the same XCD form a pair and share
+// Two work decompositions, chosen per call from the batch size:
+//  * one workgroup per cell (large batches): a persistent workgroup takes cells
+//    b, b + G, ..., evaluates every term of the cell, then sums the invariants
+//    in FP64 across the workgroup, applies the fix and writes q_out / f_out
+//    itself; its spectrum slot is reused from cell to cell.  One launch.
+//  * pairs (small batches, twice the workgroups per cell), described next.
+//
+// Pair decomposition: two workgroups on the same XCD form a pair and share
 // each of their cells; each workgroup evaluates half of the convolution terms
 // of the cell (persistent loop over the pair's cells).  Both compute the
 // forward transform and store the identical half spectrum in the cell's slot,
@@ -137,7 +144,11 @@ struct FusedArgs {
     unsigned long long* guard;   // numeric guard word, or null
 };
 
-template <int N>
+// ONE = false: the pair kernel above (partials, then k_finish).  ONE = true: one
+// workgroup evaluates all terms of a cell and applies the FP64 fix and the update
+// itself (persistent loop over cells b, b + G, ...; the spectrum slot is per
+// workgroup and reused from cell to cell).
+template <int N, bool ONE>
 __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
     constexpr int P = Cfg<N>::P;
     constexpr int NT = N * N / P;
@@ -149,22 +160,24 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
     constexpr int H = (N / 2 + 1) * N * N;   // table stride per term
     constexpr int HS = (N / 2) * N * N;      // spectrum slot per cell
     __shared__ cx<float> lds[HP * BS];
+    __shared__ double red[ONE ? 5 * (NT / 64) : 1];
 
     const int t = threadIdx.x;
     const int hi = t / N, lo = t % N;
     cx<float>* const blk = lds + hi * BS;   // this group's block
     // pairs of workgroups on one XCD: blocks b and b ^ 8
     const int b = blockIdx.x;
-    const int half = (b >> 3) & 1;
-    const int pair = (b & 7) | ((b >> 4) << 3);
+    const int half = ONE ? 0 : (b >> 3) & 1;
+    const int pair = ONE ? b : (b & 7) | ((b >> 4) << 3);
+    const int64_t stride = ONE ? (int64_t)gridDim.x : (int64_t)A.npairs;
 
-    for (int64_t cell = pair, it = 0; cell < A.ncell; cell += A.npairs, ++it) {
+    for (int64_t cell = pair, it = 0; cell < A.ncell; cell += stride, ++it) {
         // split the terms in two; for odd J the extra term alternates between
         // the halves so that the pair stays on the same cell
-        const int J0 = (it & 1) ? A.J / 2 : (A.J + 1) / 2;
+        const int J0 = ONE ? A.J : (it & 1) ? A.J / 2 : (A.J + 1) / 2;
         const int j_begin = half ? J0 : 0, j_end = half ? A.J : J0;
         const double* fc = A.f + cell * (int64_t)N3;
-        cx<float>* const fh = A.fh + cell * (int64_t)HS;
+        cx<float>* const fh = A.fh + (ONE ? (int64_t)b : cell) * (int64_t)HS;
 
         // ---------------- forward transform ----------------
         cx<float> c[P][N];
@@ -246,22 +259,41 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
         for (int j = j_begin; j < j_end; ++j) {
             const cx<float>* tj = A.tab + (size_t)j * H;
             cx<float> za[P][N];
-            // mirror pencil (-hi, -lo), kz in [0, n/2)
+            // Products Z = (a + i b) fhat.  Own pencil (hi, lo), kz in [0, n/2): from the
+            // prefetched pt, pf; mirror pencil (-hi, -lo): loaded here in four groups of
+            // kz, each group's loads issued one phase before its products, so that about
+            // a quarter of the loads is in flight while the previous quarter is consumed
+            // (all at once, or as the compiler orders them by itself, is slower).
             const int ob = opaque(((N - hi) % N) * N + ((N - lo) % N));
-            sfor<N / 2>([&](auto kI) {
+            cx<float> mt[N / 2], mf[N / 2];
+            constexpr int NG = 4, GS = (N / 2) / NG;
+            static_assert(GS * NG == N / 2, "mirror load groups");
+            auto load_mirror = [&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
                 constexpr uint32_t zo = kz * NN * sizeof(cx<float>);
-                const cx<float> ta = pt[kz], fa = pf[kz];
-                const cx<float> tb = *(const cx<float>*)((const char*)tj + (uint32_t(ob) * 8u + zo));
-                const cx<float> fb = *(const cx<float>*)((const char*)fh + (uint32_t(ob) * 8u + zo));
-                // pencil 0 = (hi, lo): kz from (hi, lo); -kz from the mirror (conjugated)
-                za[0][kz] = cmulf(ta, fa);
-                if constexpr (kz > 0) za[0][N - kz] = cmulf_conj(tb, fb);
-                if constexpr (P == 2) {
-                    // pencil 1 = (-hi, -lo): kz from the mirror, -kz from (hi, lo)
-                    za[1][kz] = cmulf(tb, fb);
-                    if constexpr (kz > 0) za[1][N - kz] = cmulf_conj(ta, fa);
-                }
+                mt[kz] = *(const cx<float>*)((const char*)tj + (uint32_t(ob) * 8u + zo));
+                mf[kz] = *(const cx<float>*)((const char*)fh + (uint32_t(ob) * 8u + zo));
+            };
+            // pencil 0 = (hi, lo): kz from (hi, lo), -kz from the mirror (conjugated);
+            // pencil 1 = (-hi, -lo): kz from the mirror, -kz from (hi, lo)
+            auto own_products = [&](auto kI) {
+                constexpr int kz = decltype(kI)::value;
+                za[0][kz] = cmulf(pt[kz], pf[kz]);
+                if constexpr (P == 2 && kz > 0) za[1][N - kz] = cmulf_conj(pt[kz], pf[kz]);
+            };
+            auto mirror_products = [&](auto kI) {
+                constexpr int kz = decltype(kI)::value;
+                if constexpr (kz > 0) za[0][N - kz] = cmulf_conj(mt[kz], mf[kz]);
+                if constexpr (P == 2) za[1][kz] = cmulf(mt[kz], mf[kz]);
+            };
+            sfor<NG + 1>([&](auto phI) {
+                constexpr int ph = decltype(phI)::value;
+                if constexpr (ph < NG)
+                    sfor<GS>([&](auto kI) { load_mirror(std::integral_constant<int, ph * GS + decltype(kI)::value>{}); });
+                if constexpr (ph == 0) sfor<N / 2>([&](auto kI) { own_products(kI); });
+                if constexpr (ph > 0)
+                    sfor<GS>([&](auto kI) { mirror_products(std::integral_constant<int, (ph - 1) * GS + decltype(kI)::value>{}); });
+                __builtin_amdgcn_sched_barrier(0);
             });
             za[0][N / 2] = cx<float>{0.0f, 0.0f};
             if constexpr (P == 2) {
@@ -324,16 +356,82 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             });
         }
 
-        // ---------------- partial sum (C layout: x, y = hi + HP p, z = lo) ----------------
-        float* mine = A.part + (cell * 2 + half) * (int64_t)N3;
-        sfor<P>([&](auto pI) {
-            constexpr int p = decltype(pI)::value;
-            float* o = mine + opaque((hi + HP * p) * N + lo);
-            sfor<N>([&](auto xI) {
-                constexpr int x = decltype(xI)::value;
-                __builtin_nontemporal_store(q[p][x], o + x * NN);
+        if constexpr (ONE) {
+            // ---------------- FP64 fix and update (C layout: x, y = hi + HP p, z = lo) ----------------
+            // thread coordinates re-derived here so that nothing computed before the term
+            // loop stays live across it (the loop needs every register)
+            const int t = opaque((int)threadIdx.x);
+            const int hi = t / N, lo = t % N;
+            const double h = A.gc->dv / A.gc->T;
+            const double uz = -1.0 + lo * h;
+            double m[5] = {0, 0, 0, 0, 0};
+            sfor<P>([&](auto pI) {
+                constexpr int p = decltype(pI)::value;
+                const double uy = -1.0 + (hi + HP * p) * h;
+                const double ryz = fma(uy, uy, uz * uz);
+                sfor<N>([&](auto xI) {
+                    constexpr int x = decltype(xI)::value;
+                    const double ux = -1.0 + x * h;
+                    const double qq = (double)q[p][x];
+                    m[0] += qq;
+                    m[1] = fma(qq, ux, m[1]);
+                    m[2] = fma(qq, uy, m[2]);
+                    m[3] = fma(qq, uz, m[3]);
+                    m[4] = fma(qq, fma(ux, ux, ryz), m[4]);
+                });
             });
-        });
+            block_sum5<NT>(m, red);
+            if (A.guard && t == 0 && !isfinite(m[0] + m[1] + m[2] + m[3] + m[4]))
+                atomicMin(A.guard, (unsigned long long)cell);
+            double lam[5];
+            solve5(*A.gc, m, lam);
+            sfor<P>([&](auto pI) {   // one pencil at a time (register budget)
+                constexpr int p = decltype(pI)::value;
+                __builtin_amdgcn_sched_barrier(0);
+                // recomputed, not kept live across the reduction: the node coordinates
+                // and the FP64 copies of q of the moment sums
+                const double h = opaque(A.gc->dv / A.gc->T);
+                const double uz = -1.0 + lo * h;
+                const double uy = -1.0 + (hi + HP * p) * h;
+                const double lyz = fma(lam[4], fma(uy, uy, uz * uz), fma(lam[2], uy, fma(lam[3], uz, lam[0])));
+                const int64_t row = cell * (int64_t)N3 + (hi + HP * p) * N + lo;
+                auto qc = [&](auto xI) {
+                    constexpr int x = decltype(xI)::value;
+                    const double ux = -1.0 + x * h;
+                    return (double)opaque(q[p][x]) - fma(lam[4], ux * ux, fma(lam[1], ux, lyz));
+                };
+                if (A.f_out) {
+                    // every load of the pencil before its first store: f_out may alias f_base
+                    double fb[N];
+                    sfor<N>([&](auto xI) {
+                        constexpr int x = decltype(xI)::value;
+                        fb[x] = __builtin_nontemporal_load(A.f_base + row + x * NN);
+                    });
+                    sfor<N>([&](auto xI) {
+                        constexpr int x = decltype(xI)::value;
+                        const double v = qc(xI);
+                        if (A.q_out) __builtin_nontemporal_store(v, A.q_out + row + x * NN);
+                        __builtin_nontemporal_store(fma(A.dt, v, fb[x]), A.f_out + row + x * NN);
+                    });
+                } else {
+                    sfor<N>([&](auto xI) {
+                        constexpr int x = decltype(xI)::value;
+                        __builtin_nontemporal_store(qc(xI), A.q_out + row + x * NN);
+                    });
+                }
+            });
+        } else {
+            // ---------------- partial sum (C layout: x, y = hi + HP p, z = lo) ----------------
+            float* mine = A.part + (cell * 2 + half) * (int64_t)N3;
+            sfor<P>([&](auto pI) {
+                constexpr int p = decltype(pI)::value;
+                float* o = mine + opaque((hi + HP * p) * N + lo);
+                sfor<N>([&](auto xI) {
+                    constexpr int x = decltype(xI)::value;
+                    __builtin_nontemporal_store(q[p][x], o + x * NN);
+                });
+            });
+        }
     }
 }
 
@@ -429,7 +527,10 @@ int grid_for(int device) {
         cus = 256;
     int per = 0;
     constexpr int NT = N * N / Cfg<N>::P;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_terms<N>, NT, 0) != hipSuccess || per <= 0) per = 1;
+    int per1 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_terms<N, false>, NT, 0) != hipSuccess || per <= 0) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, k_terms<N, true>, NT, 0) != hipSuccess || per1 <= 0) per1 = 1;
+    per = std::min(per, per1);
     int g = cus * per;
     return std::max(16, (g / 16) * 16);   // whole XCD pairs: multiple of 16 workgroups
 }
@@ -439,15 +540,6 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct WsLayout {
     size_t fh, part, total;
 };
-inline WsLayout ws_layout(int n, int64_t ncell) {
-    WsLayout w{};
-    const size_t n3 = (size_t)n * n * n;
-    w.fh = 0;
-    w.part = align256((size_t)ncell * (n / 2) * n * n * sizeof(cx<float>));
-    w.total = w.part + align256((size_t)ncell * 2 * n3 * sizeof(float));
-    return w;
-}
-
 // pairs of workgroups actually launched: a multiple of 8, at most grid/2
 inline int npairs_for(const fks_plan* p, int64_t ncell) {
     const int maxp = p->fused_grid / 2;
@@ -455,7 +547,46 @@ inline int npairs_for(const fks_plan* p, int64_t ncell) {
     return (int)std::max<int64_t>(8, ((want + 7) / 8) * 8 > maxp ? (maxp / 8) * 8 : ((want + 7) / 8) * 8);
 }
 
-// event timing (off by default): events 0..2 bracket k_terms and k_finish
+// Choice between the two decompositions, in units of one term of one cell on
+// one workgroup.  One workgroup per cell: ceil(ncell / G) rounds of J terms
+// plus the forward transform (about one term).  Pairs: rounds of half the
+// terms plus a forward transform each, and the separate finish kernel, which
+// costs about three terms per G cells (n = 32: 0.61 ms for 4096 cells against
+// 11 us per term and round).  Small batches favour pairs (twice the
+// workgroups per cell), large ones one workgroup per cell (one forward
+// transform and no partial sums in HBM).
+inline bool one_per_cell(const fks_plan* p, int64_t ncell) {
+    if (ncell <= 0) return false;
+    const int64_t G = p->fused_grid;
+    const int64_t J = p->J;
+    const int64_t c1 = (ncell + G - 1) / G * (J + 1);
+    const int64_t np = npairs_for(p, ncell);
+    const int64_t c2 = (ncell + np - 1) / np * ((J + 1) / 2 + 1) + 3 * ((ncell + G - 1) / G);
+    return c1 <= c2;
+}
+
+inline int64_t one_grid(const fks_plan* p, int64_t ncell) { return std::min<int64_t>(p->fused_grid, ncell); }
+
+// Workspace: the pair kernels keep one spectrum slot per cell plus two FP32
+// partial sums per cell; one workgroup per cell needs one slot per workgroup.
+inline WsLayout ws_layout(const fks_plan* p, int64_t ncell) {
+    const int n = p->desc.n;
+    WsLayout w{};
+    const size_t n3 = (size_t)n * n * n;
+    const size_t slot = (size_t)(n / 2) * n * n * sizeof(cx<float>);
+    w.fh = 0;
+    if (one_per_cell(p, ncell)) {
+        w.part = align256((size_t)one_grid(p, ncell) * slot);
+        w.total = w.part;
+        return w;
+    }
+    w.part = align256((size_t)ncell * slot);
+    w.total = w.part + align256((size_t)ncell * 2 * n3 * sizeof(float));
+    return w;
+}
+
+// event timing (off by default): events 0..2 bracket k_terms and k_finish (0..1
+// bracket the single kernel of the one-workgroup-per-cell decomposition)
 struct Prof {
     bool on = false;
     bool made = false;
@@ -486,7 +617,8 @@ hipError_t prof_mark(int i, hipStream_t st) {
 template <int N>
 hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
     constexpr int NT = N * N / Cfg<N>::P;
-    const WsLayout w = ws_layout(N, s.ncell);
+    const WsLayout w = ws_layout(p, s.ncell);
+    const bool one = one_per_cell(p, s.ncell);
     char* base = (char*)ws;
     FusedArgs a{};
     a.f = s.f;
@@ -504,7 +636,12 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     a.guard = p->d_guard;
     hipError_t e = prof_mark(0, st);
     if (e != hipSuccess) return e;
-    k_terms<N><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
+    if (one) {
+        k_terms<N, true><<<(unsigned)one_grid(p, s.ncell), NT, 0, st>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return prof_mark(1, st);
+    }
+    k_terms<N, false><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = prof_mark(1, st)) != hipSuccess) return e;
     k_finish<N><<<(unsigned)s.ncell, finish_threads<N>(), 0, st>>>(a);
@@ -521,11 +658,12 @@ void profile_enable(bool on) {
 
 hipError_t profile_last(double* ms, int cap, int* count) {
     *count = 0;
-    if (!g_prof.made || g_prof.count < 2) return hipSuccess;
-    hipError_t e = hipEventSynchronize(g_prof.ev[2]);
+    if (!g_prof.made || g_prof.count < 1) return hipSuccess;
+    const int last = g_prof.count;   // 1: one kernel (one workgroup per cell), 2: terms + finish
+    hipError_t e = hipEventSynchronize(g_prof.ev[last]);
     if (e != hipSuccess) return e;
     int n = 0;
-    for (int i = 0; i < 2 && n < cap; ++i) {
+    for (int i = 0; i < last && n < cap; ++i) {
         float t = 0.0f;
         if ((e = hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1])) != hipSuccess) return e;
         ms[n++] = t;
@@ -546,7 +684,7 @@ int fused_grid_size(int n, int device) {
     }
 }
 
-size_t fused_workspace_bytes(const fks_plan* p, int64_t ncell) { return ws_layout(p->desc.n, ncell).total; }
+size_t fused_workspace_bytes(const fks_plan* p, int64_t ncell) { return ws_layout(p, ncell).total; }
 
 hipError_t collide_fused(const fks_plan* p, const fks_segment& s, void* ws, size_t ws_bytes, hipStream_t st) {
     if (ws_bytes < fused_workspace_bytes(p, s.ncell)) return hipErrorInvalidValue;

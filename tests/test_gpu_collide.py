@@ -264,6 +264,84 @@ def test_multi_segment_uneven_batch():
         _check_f32(q.cpu().numpy(), r, ratio)
 
 
+# ---------------------------------------------------------------- the two fused decompositions
+
+def _kernels_of_last_call(call):
+    fks.profile_enable(True)
+    try:
+        call()
+        return len(fks.profile_last())
+    finally:
+        fks.profile_enable(False)
+
+
+def _conservation_torch(q, n, T):
+    v = torch.as_tensor(O.velocity_grid(n, T), device=q.device)
+    vx, vy, vz = torch.meshgrid(v, v, v, indexing="ij")
+    qq = q.reshape(q.shape[0], -1)
+    worst = 0.0
+    for r in (torch.ones_like(vx), vx, vy, vz, vx * vx + vy * vy + vz * vz):
+        r = r.reshape(-1)
+        worst = max(worst, float(((qq @ r).abs() / (qq.abs() @ r.abs())).max()))
+    return worst
+
+
+@pytest.mark.parametrize("n", [8, 16, 24, 32])
+def test_one_workgroup_per_cell_matches_pairs_fp64_and_oracle(n):
+    # a batch of 2 G - 7 cells (G = resident workgroups): one workgroup per cell with a
+    # ragged second round; every cell against the FP64 path, sampled cells against the
+    # oracle and against the pair decomposition (chosen for small batches)
+    plan = _plan(n=n, T=T_BOX, precision=fks.PREC_F32_FIX64)
+    G = plan.info.fused_grid
+    assert plan.info.fused == 1 and G >= 16
+    ncell = 2 * G - 7
+    f = synth.two_maxwellian_torch(n, T_BOX, ncell, "cuda", seed_offset=230 + n)
+    q = torch.empty_like(f)
+    assert _kernels_of_last_call(lambda: fks.collide(plan, f, q_out=q)) == 1
+    p64 = _plan(n=n, T=T_BOX, precision=fks.PREC_F64)
+    q64 = torch.empty_like(f)
+    fks.collide(p64, f, q_out=q64)
+    torch.cuda.synchronize()
+    err = torch.sqrt(torch.sum((q - q64) ** 2, dim=(1, 2, 3)) / torch.sum(q64 ** 2, dim=(1, 2, 3)))
+    agg = float(torch.sqrt(torch.sum((q - q64) ** 2) / torch.sum(q64 ** 2)))
+    assert agg <= 1e-5, agg
+    assert float(err.max()) <= 1e-3, (int(err.argmax()), float(err.max()))
+    assert _conservation_torch(q, n, T_BOX) <= 1e-12
+    sample = [0, G - 1, G, ncell - 1]
+    fh = f[sample].cpu().numpy()
+    ref, ratio = _oracle_qc(fh, _oplan(n, T_BOX, 1.0, 8, 4, 0), ratios=True)
+    _check_f32(q[sample].cpu().numpy(), ref, ratio)
+    # the same cells through the pair decomposition
+    fs = f[sample].contiguous()
+    qp = torch.empty_like(fs)
+    assert _kernels_of_last_call(lambda: fks.collide(plan, fs, q_out=qp)) == 2
+    torch.cuda.synchronize()
+    d = float(torch.max(torch.abs(qp - q[sample]))) / float(torch.max(torch.abs(q[sample])))
+    assert d <= 1e-5, d
+    # update in place (f_out aliases f) through the one-workgroup kernel
+    dt = 0.01
+    g = f.clone()
+    fks.collide(plan, g, f_out=g, dt_over_tau=dt)
+    torch.cuda.synchronize()
+    assert float(torch.max(torch.abs(g - (f + dt * q)))) <= 1e-15 * float(torch.max(torch.abs(f)))
+
+
+def test_one_workgroup_per_cell_numeric_guard():
+    n = 16
+    with fks.Plan(fks.Desc(n=n, T=T_BOX, precision=fks.PREC_F32_FIX64, flags=fks.FLAG_NUMERIC_GUARD)) as plan:
+        G = plan.info.fused_grid
+        ncell = 2 * G - 7
+        f = synth.two_maxwellian_torch(n, T_BOX, ncell, "cuda", seed_offset=240)
+        bad = G + 3
+        f[bad].view(-1)[17] = math.nan
+        q = torch.empty_like(f)
+        assert _kernels_of_last_call(lambda: fks.collide(plan, f, q_out=q)) == 1
+        assert plan.numeric_status() == bad
+        good = torch.ones(ncell, dtype=torch.bool, device="cuda")
+        good[bad] = False
+        assert bool(torch.isfinite(q[good]).all())
+
+
 # ---------------------------------------------------------------- full-size workload, sampled
 
 def test_full_size_hard_sphere_batch_sampled():
