@@ -13,3 +13,4 @@ Parity status of each function is stated in its docstring; the pins live in
 from .fks_oracle import *  # noqa: F401,F403
 from . import fks_oracle2d  # noqa: F401  (two-dimensional Maxwell molecules)
 from . import fks_oracle_bgk  # noqa: F401  (BGK with the conservative discrete Maxwellian)
+from . import fks_oracle_dealias  # noqa: F401  (zero-padded, de-aliased variant of the fast form)

@@ -46,6 +46,17 @@ def test_collide_batch_graph_replay(n, prec):
         _replays_match(lambda: fks.collide_batch(seg, workspace=ws), [q, g])
 
 
+def test_one_workgroup_per_cell_graph_replay():
+    # a batch large enough for the one-workgroup-per-cell kernel (ragged last round)
+    with fks.Plan(fks.Desc(n=16, T=8.0, precision=fks.PREC_F32_FIX64)) as plan:
+        ncell = 2 * plan.info.fused_grid - 7
+        f = synth.two_maxwellian_torch(16, 8.0, ncell, "cuda", seed_offset=135)
+        q, g = torch.empty_like(f), torch.empty_like(f)
+        seg = [(plan, f, q, g, ncell, 0.01)]
+        ws = torch.empty(max(fks.workspace_size(seg), 1), dtype=torch.uint8, device="cuda")
+        _replays_match(lambda: fks.collide_batch(seg, workspace=ws), [q, g])
+
+
 def test_collide2d_and_bgk_graph_replay():
     f2 = torch.as_tensor(synth.two_maxwellian_cells_2d(32, 9.0, 17, seed_offset=140), device="cuda")
     f3 = torch.as_tensor(synth.two_maxwellian_cells(32, 8.0, 5, seed_offset=141), device="cuda")
