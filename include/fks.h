@@ -56,6 +56,15 @@ typedef enum {
 /* Path selection flags (fks_plan_desc.flags). */
 #define FKS_FLAG_FORCE_GENERIC 0x1u  /* use the multi-pass path even where the fused kernel exists */
 #define FKS_FLAG_NUMERIC_GUARD 0x2u  /* record the first cell whose Q_c is not finite (fks_numeric_status) */
+/*
+ * De-aliased convolution: only pairs l + m = k exactly (k in the band
+ * -n/2 < k_i < n/2) enter Qhat_k, instead of the n-periodic sum of eq. ode.
+ * Every inverse transform and product runs on a 3n/2 grid of the same box and
+ * the band coefficients of the products are kept (zero-padding, the 3/2 rule);
+ * the FP64 fix and update are unchanged.  Multi-pass path only; dim = 3 and
+ * n in {4, 8, 12, 16, 24, 32}, else FKS_ERR_UNSUPPORTED.
+ */
+#define FKS_FLAG_DEALIAS 0x4u
 
 /*
  * Operator description (Section 3.3).  Zero / non-positive optional fields

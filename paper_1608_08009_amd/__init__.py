@@ -29,6 +29,7 @@ RULE_GAUSS = 0
 RULE_MIDPOINT = 1
 FLAG_FORCE_GENERIC = 0x1
 FLAG_NUMERIC_GUARD = 0x2
+FLAG_DEALIAS = 0x4
 BGK_EULER = 0
 BGK_EXACT = 1
 BC_PERIODIC = 0

@@ -238,19 +238,21 @@ static fks_status resolve_desc(const fks_plan_desc* in, fks_plan_desc* out) {
     if (d.rule != FKS_RULE_GAUSS && d.rule != FKS_RULE_MIDPOINT) return FKS_ERR_INVALID;
     if (d.precision != FKS_PREC_F64 && d.precision != FKS_PREC_F32_FIX64) return FKS_ERR_INVALID;
     if (d.radial_terms < 0 || d.radial_terms > 200) return FKS_ERR_INVALID;
-    if ((d.flags & ~(FKS_FLAG_FORCE_GENERIC | FKS_FLAG_NUMERIC_GUARD)) != 0) return FKS_ERR_INVALID;
+    if ((d.flags & ~(FKS_FLAG_FORCE_GENERIC | FKS_FLAG_NUMERIC_GUARD | FKS_FLAG_DEALIAS)) != 0) return FKS_ERR_INVALID;
     if (d.n <= 0) return FKS_ERR_INVALID;
     if (d.dim == 0) d.dim = 3;
     if (d.dim != 2 && d.dim != 3) return FKS_ERR_INVALID;
     if (d.dim == 2) {
         // Maxwell molecules in two velocity dimensions (Section 3.3, eq. dfor0)
         if (d.n_azim != 1 || d.radial_terms > 1) return FKS_ERR_INVALID;
-        if (d.gamma != 0.0 || (d.flags & FKS_FLAG_FORCE_GENERIC)) return FKS_ERR_UNSUPPORTED;
+        if (d.gamma != 0.0 || (d.flags & (FKS_FLAG_FORCE_GENERIC | FKS_FLAG_DEALIAS))) return FKS_ERR_UNSUPPORTED;
         if (!supported_n_2d(d.n, d.precision)) return FKS_ERR_UNSUPPORTED;
         if (d.c_gamma <= 0) d.c_gamma = 1.0 / (2.0 * kPi);
         d.radial_terms = 1;
     } else {
         if (!supported_n(d.n)) return FKS_ERR_UNSUPPORTED;
+        if ((d.flags & FKS_FLAG_DEALIAS) && !(d.n == 4 || d.n == 8 || d.n == 12 || d.n == 16 || d.n == 24 || d.n == 32))
+            return FKS_ERR_UNSUPPORTED;
         if (d.c_gamma <= 0) d.c_gamma = 1.0 / (4.0 * kPi);
     }
     if (d.R <= 0) d.R = 2.0 * d.T / (3.0 + std::sqrt(2.0));
@@ -425,6 +427,16 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
     // and accumulation; 3 per point for the update.
     double nn = (double)n * n * n;
     p->flops_per_cell = (2.0 * p->M * p->K + 2.0) * 2.5 * nn * std::log2(nn) + 7.0 * p->M * p->K * nn + 3.0 * nn;
+    if (d.flags & FKS_FLAG_DEALIAS) {
+        // per term: zero-padded inverse transforms over n^2, n n' and n'^2 lines of n' points
+        // (5 n' log2 n' flop each), the product with fhat and Re z Im z on the n' grid; once per
+        // cell: the forward and inverse n-point transforms, the truncating forward n'-point
+        // transforms and the update
+        const double np = 1.5 * n, lines = (double)n * n + (double)n * np + np * np;
+        const double fft_np = 5.0 * np * std::log2(np) * lines;
+        p->flops_per_cell = (p->M * p->K + 1.0) * (fft_np + 6.0 * nn + 2.0 * np * np * np) + fft_np +
+                            2.0 * 2.5 * nn * std::log2(nn) + 3.0 * nn;
+    }
     size_t tab_elems = (size_t)p->J * p->H * 2;
     if (hipMalloc(&p->d_tab64, tab_elems * sizeof(double)) != hipSuccess) {
         plan_free(p);
@@ -442,7 +454,7 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
             return FKS_ERR_NOMEM;
         }
         p->table_bytes += tab_elems * sizeof(float);
-        p->fused = fused_available(n) && !(d.flags & FKS_FLAG_FORCE_GENERIC);
+        p->fused = fused_available(n) && !(d.flags & (FKS_FLAG_FORCE_GENERIC | FKS_FLAG_DEALIAS));
         if (p->fused) p->fused_grid = fused_grid_size(n, p->device);
     }
     hipStream_t s = (hipStream_t)hip_stream;

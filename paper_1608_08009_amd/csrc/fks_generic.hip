@@ -10,6 +10,7 @@
 //             x-pass with acc += Re(z) Im(z) on output               (eq. ode, fast form)
 //   finish:   FP64 moments of acc, lambda = G^{-1} C acc, Q_c = acc - C^T lambda,
 //             outputs q_out = Q_c and/or f_out = f_base + dt/tau Q_c (eqs. minim1, f_coll)
+// Plans with FKS_FLAG_DEALIAS take the zero-padded variant described below.
 #include <hip/hip_runtime.h>
 
 #include "fks_common.hpp"
@@ -231,6 +232,192 @@ hipError_t run_spectrum(const double* x, double* xhat, int64_t ncell, int zero_n
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// De-aliased variant (zero-padded transforms).  The products a_j b_j and
+// f_N F^{-1}(L fhat) are sampled on a grid of NP = 3n/2 points per axis of the
+// same box, where no frequency of a product of two band-limited factors
+// (|k_i| < n/2) folds back into the band; the band coefficients of the summed
+// products then hold exactly the pairs l + m = k.  Layouts per cell (complex
+// unless noted; k = n-grid wavenumber index in FFT order, primes = NP grid):
+//   fh [kz <= n/2][kx][ky]  ->  W1 [kx][ky][z']  ->  W2 [kx][y'][z']  ->  acc [x'][y'][z'] (real)
+//   acc -> W2 [kx][y'][z'] -> W1 [kx][ky][z'] -> W2 [kx][ky][z] (n^3) -> q [x][y][z] (real)
+// ---------------------------------------------------------------------------
+
+// index of n-grid wavenumber index k (k != n/2) in the NP-grid FFT order
+template <int N, int NP>
+constexpr int pad_pos(int k) { return k < N / 2 ? k : k - N + NP; }
+
+// per term, z: Z = (a_j + i b_j) fhat along kz, zero-padded to NP, inverse transform
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(128) void d_term_z(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ tab,
+                                                cx<T>* __restrict__ w1, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
+    const int mx = (N - kx) % N, my = (N - ky) % N;
+    constexpr int H = (N / 2 + 1) * N * N;
+    const cx<T>* g = fh + (size_t)c * H;
+    cx<T> v[NP];
+    sfor<NP>([&](auto I) { v[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+    sfor<N>([&](auto I) {
+        constexpr int kz = decltype(I)::value;
+        if constexpr (kz != N / 2) {
+            cx<T> a, b;
+            if constexpr (kz < N / 2) {
+                const int h = (kz * N + kx) * N + ky;
+                a = tab[h];
+                b = g[h];
+            } else {
+                const int h = ((N - kz) * N + mx) * N + my;   // fhat(-k) = conj fhat(k); tables even in k
+                a = tab[h];
+                b = g[h];
+                b.y = -b.y;
+            }
+            v[pad_pos<N, NP>(kz)] = cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+        }
+    });
+    fft<T, NP, 1>(v);
+    cx<T>* o = w1 + ((size_t)c * N * N + kx * N + ky) * NP;
+    sfor<NP>([&](auto I) {
+        constexpr int z = decltype(I)::value;
+        o[z] = v[z];
+    });
+}
+
+// per term, y: zero-pad ky to NP, inverse transform
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(128) void d_pad_y(const cx<T>* __restrict__ w1, cx<T>* __restrict__ w2, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * NP) return;
+    const int zp = t % NP, kx = (t / NP) % N, c = t / (N * NP);
+    const cx<T>* in = w1 + ((size_t)c * N + kx) * N * NP + zp;
+    cx<T> v[NP];
+    sfor<NP>([&](auto I) { v[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+    sfor<N>([&](auto I) {
+        constexpr int ky = decltype(I)::value;
+        if constexpr (ky != N / 2) v[pad_pos<N, NP>(ky)] = in[ky * NP];
+    });
+    fft<T, NP, 1>(v);
+    cx<T>* o = w2 + ((size_t)c * N + kx) * NP * NP + zp;
+    sfor<NP>([&](auto I) {
+        constexpr int y = decltype(I)::value;
+        o[y * NP] = v[y];
+    });
+}
+
+// per term, x: zero-pad kx to NP, inverse transform, acc (+)= Re(z) Im(z) on the NP grid
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(128) void d_pad_x(const cx<T>* __restrict__ w2, T* __restrict__ acc, int C, int first) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * NP * NP) return;
+    const int zp = t % NP, yp = (t / NP) % NP, c = t / (NP * NP);
+    const cx<T>* in = w2 + (size_t)c * N * NP * NP + yp * NP + zp;
+    cx<T> v[NP];
+    sfor<NP>([&](auto I) { v[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+    sfor<N>([&](auto I) {
+        constexpr int kx = decltype(I)::value;
+        if constexpr (kx != N / 2) v[pad_pos<N, NP>(kx)] = in[kx * NP * NP];
+    });
+    fft<T, NP, 1>(v);
+    T* q = acc + (size_t)c * NP * NP * NP + yp * NP + zp;
+    sfor<NP>([&](auto I) {
+        constexpr int x = decltype(I)::value;
+        const T prod = v[x].x * v[x].y;
+        q[x * NP * NP] = first ? prod : q[x * NP * NP] + prod;
+    });
+}
+
+// after the terms, x: forward transform of the real products over x', keep the band in kx
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(128) void d_trunc_x(const T* __restrict__ acc, cx<T>* __restrict__ w2, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * NP * NP) return;
+    const int zp = t % NP, yp = (t / NP) % NP, c = t / (NP * NP);
+    const T* in = acc + (size_t)c * NP * NP * NP + yp * NP + zp;
+    cx<T> v[NP];
+    sfor<NP>([&](auto I) {
+        constexpr int x = decltype(I)::value;
+        v[x] = cx<T>{in[x * NP * NP], T(0)};
+    });
+    fft<T, NP, -1>(v);
+    cx<T>* o = w2 + (size_t)c * N * NP * NP + yp * NP + zp;
+    sfor<N>([&](auto I) {
+        constexpr int kx = decltype(I)::value;
+        if constexpr (kx == N / 2) o[kx * NP * NP] = cx<T>{T(0), T(0)};
+        else o[kx * NP * NP] = v[pad_pos<N, NP>(kx)];
+    });
+}
+
+// y: forward transform over y', keep the band in ky
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(128) void d_trunc_y(const cx<T>* __restrict__ w2, cx<T>* __restrict__ w1, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * NP) return;
+    const int zp = t % NP, kx = (t / NP) % N, c = t / (N * NP);
+    const cx<T>* in = w2 + ((size_t)c * N + kx) * NP * NP + zp;
+    cx<T> v[NP];
+    sfor<NP>([&](auto I) {
+        constexpr int y = decltype(I)::value;
+        v[y] = in[y * NP];
+    });
+    fft<T, NP, -1>(v);
+    cx<T>* o = w1 + ((size_t)c * N + kx) * N * NP + zp;
+    sfor<N>([&](auto I) {
+        constexpr int ky = decltype(I)::value;
+        if constexpr (ky == N / 2) o[ky * NP] = cx<T>{T(0), T(0)};
+        else o[ky * NP] = v[pad_pos<N, NP>(ky)];
+    });
+}
+
+// z: forward transform over z', keep the band (Nyquist planes zero), scale NP^-3, then the
+// inverse n-point transform over kz -> W2 [kx][ky][z]
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(128) void d_trunc_z_inv(const cx<T>* __restrict__ w1, cx<T>* __restrict__ w2, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
+    const cx<T>* in = w1 + ((size_t)c * N * N + kx * N + ky) * NP;
+    cx<T> v[NP];
+    sfor<NP>([&](auto I) {
+        constexpr int z = decltype(I)::value;
+        v[z] = in[z];
+    });
+    fft<T, NP, -1>(v);
+    const T s = (kx == N / 2 || ky == N / 2) ? T(0) : T(1.0 / ((double)NP * NP * NP));
+    cx<T> u[N];
+    sfor<N>([&](auto I) {
+        constexpr int kz = decltype(I)::value;
+        if constexpr (kz == N / 2) u[kz] = cx<T>{T(0), T(0)};
+        else u[kz] = cx<T>{v[pad_pos<N, NP>(kz)].x * s, v[pad_pos<N, NP>(kz)].y * s};
+    });
+    fft<T, N, 1>(u);
+    cx<T>* o = w2 + ((size_t)c * N * N + kx * N + ky) * N;
+    sfor<N>([&](auto I) {
+        constexpr int z = decltype(I)::value;
+        o[z] = u[z];
+    });
+}
+
+// x: inverse n-point transform over kx, real part -> q [x][y][z]
+template <typename T, int N>
+__global__ __launch_bounds__(128) void d_inv_x_re(const cx<T>* __restrict__ w2, T* __restrict__ q, int C) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= C * N * N) return;
+    const int z = t % N, y = (t / N) % N, c = t / (N * N);
+    const cx<T>* in = w2 + (size_t)c * N * N * N + y * N + z;
+    cx<T> v[N];
+    sfor<N>([&](auto I) {
+        constexpr int k = decltype(I)::value;
+        v[k] = in[k * N * N];
+    });
+    fft<T, N, 1>(v);
+    T* o = q + (size_t)c * N * N * N + y * N + z;
+    sfor<N>([&](auto I) {
+        constexpr int x = decltype(I)::value;
+        o[x * N * N] = v[x].x;
+    });
+}
+
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 template <typename T, int N>
@@ -266,6 +453,78 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
     return hipSuccess;
 }
 
+constexpr int kChunkDealias = 128;   // cells per pass batch of the de-aliased path
+
+struct DealiasLayout {
+    size_t fh, w1, w2, acc, total;
+};
+template <typename T>
+DealiasLayout dealias_layout(int n, int np, int chunk) {
+    DealiasLayout L{};
+    const size_t H = (size_t)(n / 2 + 1) * n * n;
+    L.fh = 0;
+    L.w1 = align256(chunk * H * sizeof(cx<T>));
+    L.w2 = L.w1 + align256((size_t)chunk * n * n * np * sizeof(cx<T>));
+    L.acc = L.w2 + align256((size_t)chunk * n * np * np * sizeof(cx<T>));
+    L.total = L.acc + align256((size_t)chunk * np * np * np * sizeof(T));
+    return L;
+}
+
+template <typename T, int N, int NP>
+hipError_t run_dealias(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
+    static_assert(N * (size_t)N * N <= (size_t)N * NP * NP, "the n^3 stages reuse W2");
+    constexpr int H = (N / 2 + 1) * N * N;
+    constexpr size_t NN = (size_t)N * N * N;
+    const int chunk = (int)std::min<int64_t>(s.ncell, kChunkDealias);
+    const DealiasLayout L = dealias_layout<T>(N, NP, chunk);
+    char* base = (char*)ws;
+    cx<T>* fh = (cx<T>*)(base + L.fh);
+    cx<T>* w1 = (cx<T>*)(base + L.w1);
+    cx<T>* w2 = (cx<T>*)(base + L.w2);
+    T* acc = (T*)(base + L.acc);
+    const cx<T>* tab = Tab<T>::get(p);
+    const int bs = 128;
+    auto grid = [&](int64_t threads) { return (unsigned)((threads + bs - 1) / bs); };
+    for (int64_t c0 = 0; c0 < s.ncell; c0 += chunk) {
+        const int C = (int)std::min<int64_t>(chunk, s.ncell - c0);
+        // forward transform of f on the n grid (W2 as the n^3 work array)
+        g_fwd_x<T, N><<<grid((int64_t)C * N * N), bs, 0, st>>>(s.f + c0 * (int64_t)NN, w2, C);
+        g_pass_y<T, N, -1><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, C);
+        g_fwd_z<T, N><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, fh, C);
+        for (int j = 0; j < p->J; ++j) {
+            d_term_z<T, N, NP><<<grid((int64_t)C * N * N), bs, 0, st>>>(fh, tab + (size_t)j * H, w1, C);
+            d_pad_y<T, N, NP><<<grid((int64_t)C * N * NP), bs, 0, st>>>(w1, w2, C);
+            d_pad_x<T, N, NP><<<grid((int64_t)C * NP * NP), bs, 0, st>>>(w2, acc, C, j == 0 ? 1 : 0);
+        }
+        // band coefficients of the products, back to the n grid
+        d_trunc_x<T, N, NP><<<grid((int64_t)C * NP * NP), bs, 0, st>>>(acc, w2, C);
+        d_trunc_y<T, N, NP><<<grid((int64_t)C * N * NP), bs, 0, st>>>(w2, w1, C);
+        d_trunc_z_inv<T, N, NP><<<grid((int64_t)C * N * N), bs, 0, st>>>(w1, w2, C);
+        g_pass_y<T, N, 1><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, C);
+        d_inv_x_re<T, N><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, acc, C);
+        const double* fb = (s.f_base ? s.f_base : s.f) + c0 * (int64_t)NN;
+        g_finish<T, N><<<C, 256, 0, st>>>(acc, fb, s.q_out ? s.q_out + c0 * (int64_t)NN : nullptr,
+                                          s.f_out ? s.f_out + c0 * (int64_t)NN : nullptr, s.dt_over_tau, p->gc,
+                                          p->d_guard, c0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t dispatch_dealias(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
+    switch (p->desc.n) {
+        case 4: return run_dealias<T, 4, 6>(p, s, ws, st);
+        case 8: return run_dealias<T, 8, 12>(p, s, ws, st);
+        case 12: return run_dealias<T, 12, 18>(p, s, ws, st);
+        case 16: return run_dealias<T, 16, 24>(p, s, ws, st);
+        case 24: return run_dealias<T, 24, 36>(p, s, ws, st);
+        case 32: return run_dealias<T, 32, 48>(p, s, ws, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t dispatch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st) {
     switch (p->desc.n) {
@@ -285,6 +544,11 @@ hipError_t dispatch(const fks_plan* p, const fks_segment& s, void* ws, hipStream
 
 size_t generic_workspace_bytes(const fks_plan* p, int64_t ncell) {
     const int n = p->desc.n;
+    if (p->desc.flags & FKS_FLAG_DEALIAS) {
+        const int chunk = (int)std::min<int64_t>(std::max<int64_t>(ncell, 1), kChunkDealias);
+        return p->desc.precision == FKS_PREC_F64 ? dealias_layout<double>(n, 3 * n / 2, chunk).total
+                                                 : dealias_layout<float>(n, 3 * n / 2, chunk).total;
+    }
     const int chunk = (int)std::min<int64_t>(ncell, kChunk);
     size_t H = (size_t)(n / 2 + 1) * n * n, NN = (size_t)n * n * n;
     if (p->desc.precision == FKS_PREC_F64)
@@ -316,6 +580,10 @@ hipError_t spectrum(const double* x, double* xhat, int64_t ncell, int n, int zer
 
 hipError_t collide_generic(const fks_plan* p, const fks_segment& s, void* ws, size_t ws_bytes, hipStream_t st) {
     if (ws_bytes < generic_workspace_bytes(p, s.ncell)) return hipErrorInvalidValue;
+    if (p->desc.flags & FKS_FLAG_DEALIAS) {
+        if (p->desc.precision == FKS_PREC_F64) return dispatch_dealias<double>(p, s, ws, st);
+        return dispatch_dealias<float>(p, s, ws, st);
+    }
     if (p->desc.precision == FKS_PREC_F64) return dispatch<double>(p, s, ws, st);
     return dispatch<float>(p, s, ws, st);
 }

@@ -54,7 +54,19 @@ def test_desc_validation_accepts_the_numeric_guard_flag():
     d2 = fks.desc2d(16, 6.0)
     d2.flags = fks.FLAG_NUMERIC_GUARD
     assert fks.desc_validate(d2) == fks.FKS_OK
-    assert fks.desc_validate(fks.Desc(n=16, T=8.0, flags=0x4)) == fks.FKS_ERR_INVALID
+    assert fks.desc_validate(fks.Desc(n=16, T=8.0, flags=0x8)) == fks.FKS_ERR_INVALID
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(n=4), fks.FKS_OK), (dict(n=32), fks.FKS_OK), (dict(n=24, gamma=0.5), fks.FKS_OK),
+    (dict(n=32, precision=fks.PREC_F64), fks.FKS_OK),
+    (dict(n=6), fks.FKS_ERR_UNSUPPORTED), (dict(n=48), fks.FKS_ERR_UNSUPPORTED),
+    (dict(n=16, gamma=0.0, n_azim=1, dim=2), fks.FKS_ERR_UNSUPPORTED),
+])
+def test_desc_validation_of_the_dealias_flag(kw, expect):
+    base = dict(T=8.0, flags=fks.FLAG_DEALIAS)
+    base.update(kw)
+    assert fks.desc_validate(fks.Desc(**base)) == expect
 
 
 def test_numeric_status_rejects_null_plan():
