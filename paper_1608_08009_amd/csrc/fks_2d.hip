@@ -16,7 +16,8 @@
 // Layout: n threads per cell, CPB cells per workgroup.  Thread i holds row
 // x = i of the cell in the physical layout (registers over y) and column
 // ky = i in the spectral layout (registers over kx); one LDS block of n rows
-// (stride n+1) per cell turns one layout into the other.
+// (stride n+1) per cell turns one layout into the other, and also stages f and
+// the outputs so that global loads and stores run along rows (coalesced).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -106,6 +107,20 @@ void tables_2d(const fks_plan_desc& d, std::vector<double>& ab) {
 
 namespace {
 
+// Orders the LDS exchanges of one cell.  A cell's n threads are consecutive, so
+// when n divides 64 they lie in one wave and a wave-level barrier suffices; for
+// other n a cell can straddle two waves and the workgroup synchronises.
+template <int N>
+__device__ __forceinline__ void cell_sync() {
+    if constexpr (64 % N == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // cells per workgroup: n threads each, at most 256 threads and 128 KiB of LDS
 template <typename R, int N>
 constexpr int cells_per_block() {
@@ -134,7 +149,7 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
     constexpr int RS = N + 1;
     constexpr int NN = N * N;
     __shared__ cx<R> lds[CPB * N * RS];
-    static_assert(CPB * N * 4 * sizeof(double) <= sizeof(lds), "reduction buffer");
+    static_assert(N * 4 * sizeof(double) <= N * RS * sizeof(cx<R>), "reduction buffer inside a cell's block");
     const int t = threadIdx.x;
     const int c = t / N, i = t % N;
     const int64_t cell = (int64_t)blockIdx.x * CPB + c;
@@ -143,26 +158,34 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
     const cx<R>* const tab = (const cx<R>*)A.tab;
 
     // ---- forward transform: row x = i over y, then columns over x ----
+    // coalesced load: lane i reads element y = i of every row; the cell's block turns
+    // the columns into rows
     cx<R> z[N];
     {
-        const double* fr = A.f + (live ? cell : 0) * (int64_t)NN + i * N;
+        const double* fc = A.f + (live ? cell : 0) * (int64_t)NN + i;
+        sfor<N>([&](auto xI) {
+            constexpr int x = decltype(xI)::value;
+            blk[x * RS + i] = cx<R>{live ? (R)fc[x * N] : R(0), R(0)};
+        });
+        cell_sync<N>();
         sfor<N>([&](auto yI) {
             constexpr int y = decltype(yI)::value;
-            z[y] = cx<R>{live ? (R)fr[y] : R(0), R(0)};
+            z[y] = blk[i * RS + y];
         });
+        cell_sync<N>();
     }
     fft<R, N, -1>(z);
     sfor<N>([&](auto kI) {   // row layout -> column layout: blk[ky][x]
         constexpr int k = decltype(kI)::value;
         blk[k * RS + i] = z[k];
     });
-    __syncthreads();
+    cell_sync<N>();
     cx<R> fh[N];   // column ky = i, registers over kx
     sfor<N>([&](auto kI) {
         constexpr int k = decltype(kI)::value;
         fh[k] = blk[i * RS + k];
     });
-    __syncthreads();
+    cell_sync<N>();
     fft<R, N, -1>(fh);
     {
         const R s = (i == N / 2) ? R(0) : R(1) / R(NN);
@@ -178,22 +201,36 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
     sfor<N>([&](auto yI) { q[decltype(yI)::value] = R(0); });
     for (int j = 0; j < A.J; ++j) {
         const cx<R>* tj = tab + (size_t)j * NN + i;
-        sfor<N>([&](auto kI) {
-            constexpr int k = decltype(kI)::value;
-            const cx<R> ab = tj[k * N];   // (a, b) at (kx = k, ky = i)
-            z[k] = cx<R>{ab.x * fh[k].x - ab.y * fh[k].y, ab.x * fh[k].y + ab.y * fh[k].x};
+        // (a, b) at (kx = k, ky = i), loaded in groups of kx, each group one scheduling
+        // phase ahead of its products (left alone, the compiler waits on every load of
+        // the FP64 kernel before issuing the next)
+        constexpr int NG = (N % 4 == 0) ? 4 : 1, GS = N / NG;
+        cx<R> ab[N];
+        sfor<NG + 1>([&](auto phI) {
+            constexpr int ph = decltype(phI)::value;
+            if constexpr (ph < NG)
+                sfor<GS>([&](auto kI) {
+                    constexpr int k = ph * GS + decltype(kI)::value;
+                    ab[k] = tj[k * N];
+                });
+            if constexpr (ph > 0)
+                sfor<GS>([&](auto kI) {
+                    constexpr int k = (ph - 1) * GS + decltype(kI)::value;
+                    z[k] = cx<R>{ab[k].x * fh[k].x - ab[k].y * fh[k].y, ab[k].x * fh[k].y + ab[k].y * fh[k].x};
+                });
+            __builtin_amdgcn_sched_barrier(0);
         });
         fft<R, N, 1>(z);   // over kx: column ky = i, registers over x
         sfor<N>([&](auto xI) {
             constexpr int x = decltype(xI)::value;
             blk[x * RS + i] = z[x];
         });
-        __syncthreads();
+        cell_sync<N>();
         sfor<N>([&](auto kI) {
             constexpr int k = decltype(kI)::value;
             z[k] = blk[i * RS + k];
         });
-        __syncthreads();
+        cell_sync<N>();
         fft<R, N, 1>(z);   // over ky: row x = i, registers over y
         sfor<N>([&](auto yI) {
             constexpr int y = decltype(yI)::value;
@@ -214,14 +251,16 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         m[2] = fma(qq, uy, m[2]);
         m[3] = fma(qq, fma(ux, ux, uy * uy), m[3]);
     });
-    double* red = (double*)lds;
+    // the cell's own LDS block holds its partial sums: other cells (possibly in other
+    // waves) may still be reading their blocks
+    double* red = (double*)blk;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) red[(c * N + i) * 4 + a] = m[a];
-    __syncthreads();
+    for (int a = 0; a < 4; ++a) red[i * 4 + a] = m[a];
+    cell_sync<N>();
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < N; ++k)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) s[a] += red[(c * N + k) * 4 + a];
+        for (int a = 0; a < 4; ++a) s[a] += red[k * 4 + a];
     double lam[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -230,17 +269,40 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         for (int b = 0; b < 4; ++b) v = fma(g.ginv[a * 4 + b], s[b], v);
         lam[a] = v;
     }
-    if (!live) return;
-    if (A.guard && i == 0 && !isfinite(s[0] + s[1] + s[2] + s[3])) atomicMin(A.guard, (unsigned long long)cell);
-    const int64_t base = cell * (int64_t)NN + i * N;
+    if (live && A.guard && i == 0 && !isfinite(s[0] + s[1] + s[2] + s[3]))
+        atomicMin(A.guard, (unsigned long long)cell);
+    // Q_c of row x = i into the block (one double per slot), then coalesced stores: lane i
+    // writes element y = i of every row
+    constexpr int W = sizeof(cx<R>) / sizeof(double);
+    double* const bd = (double*)blk;
+    cell_sync<N>();   // every thread has read the partial sums
     const double lx = fma(lam[1], ux, lam[0]);
     sfor<N>([&](auto yI) {
         constexpr int y = decltype(yI)::value;
         const double uy = -1.0 + y * h;
-        const double qc = (double)q[y] - (lx + lam[2] * uy + lam[3] * fma(ux, ux, uy * uy));
-        if (A.q_out) A.q_out[base + y] = qc;
-        if (A.f_out) A.f_out[base + y] = fma(A.dt, qc, A.f_base[base + y]);
+        bd[(i * RS + y) * W] = (double)q[y] - (lx + lam[2] * uy + lam[3] * fma(ux, ux, uy * uy));
     });
+    cell_sync<N>();
+    if (!live) return;
+    const int64_t base = cell * (int64_t)NN + i;
+    if (A.f_out) {
+        double fb[N];   // every load before the first store: f_out may alias f_base
+        sfor<N>([&](auto xI) {
+            constexpr int x = decltype(xI)::value;
+            fb[x] = A.f_base[base + x * N];
+        });
+        sfor<N>([&](auto xI) {
+            constexpr int x = decltype(xI)::value;
+            const double qc = bd[(x * RS + i) * W];
+            if (A.q_out) A.q_out[base + x * N] = qc;
+            A.f_out[base + x * N] = fma(A.dt, qc, fb[x]);
+        });
+    } else {
+        sfor<N>([&](auto xI) {
+            constexpr int x = decltype(xI)::value;
+            A.q_out[base + x * N] = bd[(x * RS + i) * W];
+        });
+    }
 }
 
 template <typename R, int N>
