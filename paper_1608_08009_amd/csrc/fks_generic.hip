@@ -6,8 +6,9 @@
 //   forward:  x-pass, y-pass, z-pass -> fhat (half spectrum kz in [0, n/2],
 //             scaled by n^-3, Nyquist planes zeroed)                 (eq. FC)
 //   per term j (M*K gain terms, then the loss term):
-//             z-pass with Z = (a_j + i b_j) fhat on input, y-pass,
-//             x-pass with acc += Re(z) Im(z) on output               (eq. ode, fast form)
+//             fused z- and y-pass per (cell, kx) plane with Z = (a_j + i b_j) fhat
+//             on input, then the x-pass with acc += Re(z) Im(z) on output
+//             (eq. ode, fast form)
 //   finish:   FP64 moments of acc, lambda = G^{-1} C acc, Q_c = acc - C^T lambda,
 //             outputs q_out = Q_c and/or f_out = f_base + dt/tau Q_c (eqs. minim1, f_coll)
 // Plans with FKS_FLAG_DEALIAS take the zero-padded variant described below.
@@ -92,15 +93,41 @@ __global__ __launch_bounds__(128) void g_fwd_z(const cx<T>* __restrict__ work, c
     });
 }
 
+// z and y inverse passes of one term fused, one (cell, kx) plane per group of n
+// threads: thread ky computes Z = (a_j + i b_j) fhat over kz and its inverse
+// transform over z; the plane goes through LDS (real parts, then imaginary parts,
+// which halves the LDS per plane); thread z then transforms over y and writes
+// work[c][kx][y][z] with consecutive lanes on consecutive z.
+template <int N>
+constexpr int zy_planes() { return N <= 32 ? 128 / N : 1; }
+
 template <typename T, int N>
-__global__ __launch_bounds__(128) void g_inv_z(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ tab,
-                                               cx<T>* __restrict__ work, int C) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= C * N * N) return;
-    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
+__device__ __forceinline__ void plane_sync() {
+    if constexpr (64 % N == 0) {   // a plane's n threads lie in one wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(zy_planes<N>() * N) void g_inv_zy(const cx<T>* __restrict__ fh,
+                                                               const cx<T>* __restrict__ tab,
+                                                               cx<T>* __restrict__ work, int C) {
+    constexpr int PP = zy_planes<N>();
+    constexpr int RS = N + 1;
+    __shared__ T lds[PP * N * RS];
+    const int pl = threadIdx.x / N, i = threadIdx.x % N;
+    const int64_t plane = (int64_t)blockIdx.x * PP + pl;   // c * N + kx
+    const bool live = plane < (int64_t)C * N;
+    const int kx = (int)(plane % N);
+    const int64_t c = live ? plane / N : 0;
+    const int ky = i;
     const int mx = (N - kx) % N, my = (N - ky) % N;
     constexpr int H = (N / 2 + 1) * N * N;
-    const cx<T>* g = fh + (size_t)c * H;
+    const cx<T>* g = fh + c * H;
     cx<T> v[N];
     sfor<N>([&](auto I) {
         constexpr int kz = decltype(I)::value;
@@ -117,11 +144,22 @@ __global__ __launch_bounds__(128) void g_inv_z(const cx<T>* __restrict__ fh, con
         }
         v[kz] = cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
     });
-    fft<T, N, 1>(v);
-    cx<T>* o = work + (size_t)c * N * N * N + (kx * N + ky) * N;
+    fft<T, N, 1>(v);   // over kz: row ky = i, registers over z
+    T* const blk = lds + pl * N * RS;
+    cx<T> u[N];
+    sfor<N>([&](auto I) { blk[i * RS + decltype(I)::value] = v[decltype(I)::value].x; });
+    plane_sync<T, N>();
+    sfor<N>([&](auto I) { u[decltype(I)::value].x = blk[decltype(I)::value * RS + i]; });
+    plane_sync<T, N>();
+    sfor<N>([&](auto I) { blk[i * RS + decltype(I)::value] = v[decltype(I)::value].y; });
+    plane_sync<T, N>();
+    sfor<N>([&](auto I) { u[decltype(I)::value].y = blk[decltype(I)::value * RS + i]; });
+    fft<T, N, 1>(u);   // over ky: column z = i, registers over y
+    if (!live) return;
+    cx<T>* o = work + (c * N + kx) * N * N + i;
     sfor<N>([&](auto I) {
-        constexpr int z = decltype(I)::value;
-        o[z] = v[z];
+        constexpr int y = decltype(I)::value;
+        o[y * N] = u[y];
     });
 }
 
@@ -139,10 +177,21 @@ __global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work, T
     });
     fft<T, N, 1>(v);
     T* q = acc + (size_t)c * N * N * N + y * N + z;
-    sfor<N>([&](auto I) {
-        constexpr int x = decltype(I)::value;
-        T prod = v[x].x * v[x].y;
-        q[x * N * N] = first ? prod : q[x * N * N] + prod;
+    // accumulator read-modify-write in groups of x, fenced so that the compiler does not
+    // load every accumulator at once (which costs the FP64 kernel half its occupancy)
+    constexpr int G = (N % 8 == 0) ? 8 : N;
+    sfor<N / G>([&](auto gI) {
+        constexpr int g0 = decltype(gI)::value * G;
+        T prod[G];
+        sfor<G>([&](auto I) {
+            constexpr int x = g0 + decltype(I)::value;
+            prod[decltype(I)::value] = first ? v[x].x * v[x].y : q[x * N * N] + v[x].x * v[x].y;
+        });
+        sfor<G>([&](auto I) {
+            constexpr int x = g0 + decltype(I)::value;
+            q[x * N * N] = prod[decltype(I)::value];
+        });
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -438,9 +487,10 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
         g_fwd_x<T, N><<<grid, bs, 0, st>>>(f, work, C);
         g_pass_y<T, N, -1><<<grid, bs, 0, st>>>(work, C);
         g_fwd_z<T, N><<<grid, bs, 0, st>>>(work, fh, C);
+        constexpr int PP = zy_planes<N>();
+        const unsigned gzy = (unsigned)(((int64_t)C * N + PP - 1) / PP);
         for (int j = 0; j < p->J; ++j) {
-            g_inv_z<T, N><<<grid, bs, 0, st>>>(fh, tab + (size_t)j * H, work, C);
-            g_pass_y<T, N, 1><<<grid, bs, 0, st>>>(work, C);
+            g_inv_zy<T, N><<<gzy, PP * N, 0, st>>>(fh, tab + (size_t)j * H, work, C);
             g_inv_x<T, N><<<grid, bs, 0, st>>>(work, acc, C, j == 0 ? 1 : 0);
         }
         const double* fb = (s.f_base ? s.f_base : s.f) + c0 * (int64_t)NN;
