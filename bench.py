@@ -50,6 +50,53 @@ def _oracle_worker(args):
     return out, time.perf_counter() - t0
 
 
+def _oracle_extra_worker(args):
+    """Times the oracle (as it stands) on a bounded sample of one extra workload, one core:
+    cells in order until about 2.5 s of oracle time (inputs generated beforehand)."""
+    kind, = args
+    import oracle as O
+    import synth
+    budget = 2.5
+    if kind == "collide2d":
+        n, T, A = 32, 9.0, 8
+        f = synth.two_maxwellian_cells_2d(n, T, 8192, seed_offset=123)
+        p2 = O.fks_oracle2d.make_plan2(n, T, A)
+        step = lambda g: g + 0.02 * O.fks_oracle2d.conserve2_Q(O.fks_oracle2d.collide2_fast64(g, p2), n, T)  # noqa: E731
+        pts = n * n
+    elif kind == "bgk":
+        f = synth.two_maxwellian_cells(N_V, T_BOX, NCELL, first=0, count=512)
+        nu = 2.0 * (2.0 * T_BOX / (3.0 + math.sqrt(2.0)))   # mu = 4 pi C (2R)^gamma, C = 1/(4 pi), gamma = 1
+        step = lambda g: O.fks_oracle_bgk.bgk_step(g, N_V, T_BOX, 3, nu, DT_OVER_TAU)  # noqa: E731
+        pts = N_V ** 3
+    elif kind == "dealias":
+        f = synth.two_maxwellian_cells(N_V, T_BOX, NCELL, first=0, count=8)
+        op = O.make_plan(N_V, T_BOX, n_polar=N_POLAR, n_azim=N_AZIM)
+        step = lambda g: g + DT_OVER_TAU * O.conserve_Q(O.fks_oracle_dealias.collide_dealias_fast64(g, op),  # noqa: E731
+                                                        N_V, T_BOX)
+        pts = N_V ** 3
+    else:
+        raise ValueError(kind)
+    count, t0 = 0, time.perf_counter()
+    while count < len(f) and (count == 0 or time.perf_counter() - t0 < budget):
+        step(f[count])
+        count += 1
+    return kind, count, pts, time.perf_counter() - t0
+
+
+def cpu_extras(kinds):
+    """Oracle timings beside the extra GPU lines: {kind: cpu_baseline dict}, one process per kind."""
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(len(kinds)) as pool:
+        res = pool.map(_oracle_extra_worker, [(k,) for k in kinds])
+    out = {}
+    for kind, count, pts, t in res:
+        unit = "cells·N²/s" if kind == "collide2d" else UNIT
+        out[kind] = {"value": count * pts / t, "unit": unit, "cores": 1, "kind": "oracle",
+                     "sample": f"{count} cells of the same workload, numpy FP64, one single-threaded "
+                               f"process ({t:.1f} s)"}
+    return out
+
+
 def cpu_baseline(sample_cells, workers):
     """Times the oracle (as it stands) on the sample; returns (result dict, {cell: (Q_c, ratio)})."""
     chunks = [sample_cells[i::workers] for i in range(workers)]
@@ -97,6 +144,19 @@ def _traffic_per_launch():
     if rec.get("source_hash") != _fused_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def _valu_busy():
+    """VALU-busy fraction of the terms kernel from the committed SQ counter summary, or None
+    if the kernel sources changed since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "sq_k_terms32_hs4096.json")) as fp:
+            rec = json.load(fp)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _fused_source_hash():
+        return None
+    return rec.get("valu_busy")
 
 
 def main():
@@ -320,6 +380,16 @@ def main():
                   "per_cell_max": max(per), "per_cell_median": float(np.median(per)),
                   "max_cancellation_ratio": float(ratios.max())}
 
+    # the oracle beside the extra lines (bounded samples, one core each)
+    if args.extras and args.cpu_sample > 0:
+        extra_cpu = cpu_extras(["collide2d", "bgk", "dealias"])
+        if d2_line is not None:
+            d2_line["cpu_baseline"] = extra_cpu["collide2d"]
+        if bgk_line is not None:
+            bgk_line["cpu_baseline"] = extra_cpu["bgk"]
+        if dealias_line is not None:
+            dealias_line["cpu_baseline"] = extra_cpu["dealias"]
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -344,7 +414,7 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
                      "peak_unpacked_fma": PEAK_FP32_UNPACKED_TFLOPS,
                      "frac_unpacked_fma": round(achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4),
-                     "traffic": _traffic_per_launch(), "kernel": kernel_name,
+                     "traffic": _traffic_per_launch(), "valu_busy_counters": _valu_busy(), "kernel": kernel_name,
                      "avg_launch_ms": round(terms_ms, 4), "finish_kernel_ms": round(finish_ms, 4),
                      "call_ms": round(avg_call_ms, 4), "flops_per_cell": plan.info.flops_per_cell,
                      "source_hash": _fused_source_hash()},

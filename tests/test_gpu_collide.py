@@ -318,8 +318,14 @@ def test_one_workgroup_per_cell_matches_pairs_fp64_and_oracle(n):
     torch.cuda.synchronize()
     d = float(torch.max(torch.abs(qp - q[sample]))) / float(torch.max(torch.abs(q[sample])))
     assert d <= 1e-5, d
-    # update in place (f_out aliases f) through the one-workgroup kernel
+    # q_out and f_out from one call
     dt = 0.01
+    q2, g2 = torch.empty_like(f), torch.empty_like(f)
+    fks.collide(plan, f, q_out=q2, f_out=g2, dt_over_tau=dt)
+    torch.cuda.synchronize()
+    assert torch.equal(q2, q)
+    assert float(torch.max(torch.abs(g2 - (f + dt * q)))) <= 1e-15 * float(torch.max(torch.abs(f)))
+    # update in place (f_out aliases f) through the one-workgroup kernel
     g = f.clone()
     fks.collide(plan, g, f_out=g, dt_over_tau=dt)
     torch.cuda.synchronize()
