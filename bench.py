@@ -345,11 +345,11 @@ def main():
                             "ms": round(msd, 3), "value": cd * N_V ** 3 / (msd * 1e-3), "unit": UNIT,
                             "algorithmic_tflops": round(pd.info.flops_per_cell * cd / (msd * 1e-3) / 1e12, 2)}
             # bytes the multi-pass design moves through HBM (FP32 work arrays, FP64 f):
-            # per term the padded z, y and x passes; per cell the forward transform, the
+            # per term the fused padded z-y pass and the x pass; per cell the forward transform, the
             # truncating passes, the inverse n-point passes and the fix
             n, npd, cxb, rb = N_V, 3 * N_V // 2, 8, 4
             h_half = (n // 2 + 1) * n * n
-            per_term = (h_half * cxb + 2 * n * n * npd * cxb + 2 * n * npd * npd * cxb + 2 * npd ** 3 * rb)
+            per_term = (h_half * cxb + 2 * n * npd * npd * cxb + 2 * npd ** 3 * rb)   # fused z-y, then x
             per_cell = (n ** 3 * (8 + 3 * cxb) + h_half * cxb                       # forward
                         + npd ** 3 * rb + 2 * n * npd * npd * cxb + 2 * n * n * npd * cxb + n ** 3 * cxb
                         + 3 * n ** 3 * cxb + n ** 3 * rb                               # back to the n grid

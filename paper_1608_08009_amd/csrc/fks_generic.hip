@@ -288,71 +288,13 @@ hipError_t run_spectrum(const double* x, double* xhat, int64_t ncell, int zero_n
 // (|k_i| < n/2) folds back into the band; the band coefficients of the summed
 // products then hold exactly the pairs l + m = k.  Layouts per cell (complex
 // unless noted; k = n-grid wavenumber index in FFT order, primes = NP grid):
-//   fh [kz <= n/2][kx][ky]  ->  W1 [kx][ky][z']  ->  W2 [kx][y'][z']  ->  acc [x'][y'][z'] (real)
+//   fh [kz <= n/2][kx][ky]  ->  W2 [kx][y'][z'] (z and y fused)  ->  acc [x'][y'][z'] (real)
 //   acc -> W2 [kx][y'][z'] -> W1 [kx][ky][z'] -> W2 [kx][ky][z] (n^3) -> q [x][y][z] (real)
 // ---------------------------------------------------------------------------
 
 // index of n-grid wavenumber index k (k != n/2) in the NP-grid FFT order
 template <int N, int NP>
 constexpr int pad_pos(int k) { return k < N / 2 ? k : k - N + NP; }
-
-// per term, z: Z = (a_j + i b_j) fhat along kz, zero-padded to NP, inverse transform
-template <typename T, int N, int NP>
-__global__ __launch_bounds__(128) void d_term_z(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ tab,
-                                                cx<T>* __restrict__ w1, int C) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= C * N * N) return;
-    const int ky = t % N, kx = (t / N) % N, c = t / (N * N);
-    const int mx = (N - kx) % N, my = (N - ky) % N;
-    constexpr int H = (N / 2 + 1) * N * N;
-    const cx<T>* g = fh + (size_t)c * H;
-    cx<T> v[NP];
-    sfor<NP>([&](auto I) { v[decltype(I)::value] = cx<T>{T(0), T(0)}; });
-    sfor<N>([&](auto I) {
-        constexpr int kz = decltype(I)::value;
-        if constexpr (kz != N / 2) {
-            cx<T> a, b;
-            if constexpr (kz < N / 2) {
-                const int h = (kz * N + kx) * N + ky;
-                a = tab[h];
-                b = g[h];
-            } else {
-                const int h = ((N - kz) * N + mx) * N + my;   // fhat(-k) = conj fhat(k); tables even in k
-                a = tab[h];
-                b = g[h];
-                b.y = -b.y;
-            }
-            v[pad_pos<N, NP>(kz)] = cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-        }
-    });
-    fft<T, NP, 1>(v);
-    cx<T>* o = w1 + ((size_t)c * N * N + kx * N + ky) * NP;
-    sfor<NP>([&](auto I) {
-        constexpr int z = decltype(I)::value;
-        o[z] = v[z];
-    });
-}
-
-// per term, y: zero-pad ky to NP, inverse transform
-template <typename T, int N, int NP>
-__global__ __launch_bounds__(128) void d_pad_y(const cx<T>* __restrict__ w1, cx<T>* __restrict__ w2, int C) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= C * N * NP) return;
-    const int zp = t % NP, kx = (t / NP) % N, c = t / (N * NP);
-    const cx<T>* in = w1 + ((size_t)c * N + kx) * N * NP + zp;
-    cx<T> v[NP];
-    sfor<NP>([&](auto I) { v[decltype(I)::value] = cx<T>{T(0), T(0)}; });
-    sfor<N>([&](auto I) {
-        constexpr int ky = decltype(I)::value;
-        if constexpr (ky != N / 2) v[pad_pos<N, NP>(ky)] = in[ky * NP];
-    });
-    fft<T, NP, 1>(v);
-    cx<T>* o = w2 + ((size_t)c * N + kx) * NP * NP + zp;
-    sfor<NP>([&](auto I) {
-        constexpr int y = decltype(I)::value;
-        o[y * NP] = v[y];
-    });
-}
 
 // per term, x: zero-pad kx to NP, inverse transform, acc (+)= Re(z) Im(z) on the NP grid
 template <typename T, int N, int NP>
@@ -369,11 +311,92 @@ __global__ __launch_bounds__(128) void d_pad_x(const cx<T>* __restrict__ w2, T* 
     });
     fft<T, NP, 1>(v);
     T* q = acc + (size_t)c * NP * NP * NP + yp * NP + zp;
-    sfor<NP>([&](auto I) {
-        constexpr int x = decltype(I)::value;
-        const T prod = v[x].x * v[x].y;
-        q[x * NP * NP] = first ? prod : q[x * NP * NP] + prod;
+    // accumulator read-modify-write in fenced groups of x (as in g_inv_x)
+    constexpr int G = (NP % 8 == 0) ? 8 : (NP % 6 == 0 ? 6 : NP);
+    sfor<NP / G>([&](auto gI) {
+        constexpr int g0 = decltype(gI)::value * G;
+        T prod[G];
+        sfor<G>([&](auto I) {
+            constexpr int x = g0 + decltype(I)::value;
+            prod[decltype(I)::value] = first ? v[x].x * v[x].y : q[x * NP * NP] + v[x].x * v[x].y;
+        });
+        sfor<G>([&](auto I) {
+            constexpr int x = g0 + decltype(I)::value;
+            q[x * NP * NP] = prod[decltype(I)::value];
+        });
+        __builtin_amdgcn_sched_barrier(0);
     });
+}
+
+// per term, z and y fused: one wave per (cell, kx) plane.  Lanes ky < n compute Z over kz,
+// zero-padded to NP, and transform over z'; the plane goes through LDS (real parts, then
+// imaginary parts); lanes z' < NP then zero-pad ky, transform over y' and write
+// W2[c][kx][y'][z'] with consecutive lanes on consecutive z'.
+template <typename T, int N, int NP>
+__global__ __launch_bounds__(64) void d_term_zy(const cx<T>* __restrict__ fh, const cx<T>* __restrict__ tab,
+                                                cx<T>* __restrict__ w2, int C) {
+    static_assert(NP <= 64 && N <= NP, "one wave per plane");
+    constexpr int RS = NP + 1;
+    __shared__ T lds[N * RS];
+    const int i = threadIdx.x;
+    const int64_t plane = blockIdx.x;   // c * N + kx
+    const int kx = (int)(plane % N);
+    const int64_t c = plane / N;
+    constexpr int H = (N / 2 + 1) * N * N;
+    cx<T> v[NP];
+    if (i < N) {
+        const int ky = i, mx = (N - kx) % N, my = (N - ky) % N;
+        const cx<T>* g = fh + c * H;
+        sfor<NP>([&](auto I) { v[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+        sfor<N>([&](auto I) {
+            constexpr int kz = decltype(I)::value;
+            if constexpr (kz != N / 2) {
+                cx<T> a, b;
+                if constexpr (kz < N / 2) {
+                    const int h = (kz * N + kx) * N + ky;
+                    a = tab[h];
+                    b = g[h];
+                } else {
+                    const int h = ((N - kz) * N + mx) * N + my;   // fhat(-k) = conj fhat(k); tables even
+                    a = tab[h];
+                    b = g[h];
+                    b.y = -b.y;
+                }
+                v[pad_pos<N, NP>(kz)] = cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+            }
+        });
+        fft<T, NP, 1>(v);   // over z': row ky = i
+        sfor<NP>([&](auto I) { lds[i * RS + decltype(I)::value] = v[decltype(I)::value].x; });
+    }
+    auto wsync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    wsync();
+    cx<T> u[NP];
+    sfor<NP>([&](auto I) { u[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+    if (i < NP) {
+        sfor<N>([&](auto I) {
+            constexpr int ky = decltype(I)::value;
+            if constexpr (ky != N / 2) u[pad_pos<N, NP>(ky)].x = lds[ky * RS + i];
+        });
+    }
+    wsync();
+    if (i < N) sfor<NP>([&](auto I) { lds[i * RS + decltype(I)::value] = v[decltype(I)::value].y; });
+    wsync();
+    if (i < NP) {
+        sfor<N>([&](auto I) {
+            constexpr int ky = decltype(I)::value;
+            if constexpr (ky != N / 2) u[pad_pos<N, NP>(ky)].y = lds[ky * RS + i];
+        });
+        fft<T, NP, 1>(u);   // over y': column z' = i
+        cx<T>* o = w2 + (c * N + kx) * NP * NP + i;
+        sfor<NP>([&](auto I) {
+            constexpr int y = decltype(I)::value;
+            o[y * NP] = u[y];
+        });
+    }
 }
 
 // after the terms, x: forward transform of the real products over x', keep the band in kx
@@ -542,8 +565,7 @@ hipError_t run_dealias(const fks_plan* p, const fks_segment& s, void* ws, hipStr
         g_pass_y<T, N, -1><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, C);
         g_fwd_z<T, N><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, fh, C);
         for (int j = 0; j < p->J; ++j) {
-            d_term_z<T, N, NP><<<grid((int64_t)C * N * N), bs, 0, st>>>(fh, tab + (size_t)j * H, w1, C);
-            d_pad_y<T, N, NP><<<grid((int64_t)C * N * NP), bs, 0, st>>>(w1, w2, C);
+            d_term_zy<T, N, NP><<<(unsigned)(C * N), 64, 0, st>>>(fh, tab + (size_t)j * H, w2, C);
             d_pad_x<T, N, NP><<<grid((int64_t)C * NP * NP), bs, 0, st>>>(w2, acc, C, j == 0 ? 1 : 0);
         }
         // band coefficients of the products, back to the n grid
