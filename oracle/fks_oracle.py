@@ -51,7 +51,7 @@ __all__ = [
     "RadialTerms", "radial_terms", "Plan", "make_plan", "build_tables", "spectrum",
     "synthesize", "collide_fast64", "collide_direct", "collision_basis",
     "conserve_Q", "project", "moments", "primitive", "relative_l2",
-    "transport_shift", "transport_offsets_step", "euler_update",
+    "transport_shift", "transport_offsets_step", "euler_update", "exp_euler_update",
 ]
 
 
@@ -432,6 +432,18 @@ def primitive(U: np.ndarray):
 def euler_update(f: np.ndarray, Qc: np.ndarray, dt_over_tau: float) -> np.ndarray:
     """f^{n+1} = f* + (dt/tau) Q_c (eq. f_coll with the rescaling of Part 2)."""
     return f + dt_over_tau * Qc
+
+
+def exp_euler_update(f: np.ndarray, Qc: np.ndarray, dt_over_tau: float, mu: float) -> np.ndarray:
+    """Exponential Euler step of the collision ODE for stiff (small tau) collisions.
+
+    Reading (Section 3.1 leaves the stiff case to the integrators of its references):
+    split Q = [Q + mu (f - M)] - mu (f - M) with M the local Maxwellian, which the
+    collision step does not change, and integrate the linear part exactly over
+    h = dt/tau with the rest frozen.  Then f - M cancels and the step is
+    f^{n+1} = f* + ((1 - exp(-mu h)) / mu) Q_c: Euler with its step capped at 1/mu.
+    For BGK (Q = nu (M - f), mu = nu) this is the exact relaxation step."""
+    return f + (-math.expm1(-mu * dt_over_tau) / mu) * Qc
 
 
 def relative_l2(a: np.ndarray, b: np.ndarray) -> float:

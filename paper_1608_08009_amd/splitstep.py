@@ -10,7 +10,13 @@ integrators as possible; Section 3.1):
     transport step (the transport shift is exact for any dt);
   * collision="rk2": the midpoint rule for the collision ODE,
     f^{n+1} = f* + (dt/tau) Q_c(f* + (dt/2tau) Q_c(f*)), as two calls of
-    fks_collide_batch (the second with f_base = f*).
+    fks_collide_batch (the second with f_base = f*);
+  * collision="exp": the exponential Euler step for stiff collisions (small
+    tau; the paper defers to the integrators of its references).  With Q split
+    as [Q + mu (f - M)] - mu (f - M), M the local Maxwellian, the step is
+    f^{n+1} = f* + ((1 - exp(-mu dt/tau)) / mu) Q_c(f*): one call whose step
+    never exceeds 1/mu.  mu bounds the loss frequency, e.g.
+    4 pi C_gamma (2R)^gamma rho_max.
 Every step runs in the HIP library; this module only sequences the calls.
 """
 from __future__ import annotations
@@ -48,10 +54,13 @@ class SplitStepper:
     """Owns the ping-pong buffers, the workspace and the transport offsets of one run."""
 
     def __init__(self, plan: Plan, space: Space, f, bc_f=None, scheme: str = "lie",
-                 collision: str = "euler"):
+                 collision: str = "euler", mu: float = 0.0):
         import torch
-        if scheme not in ("lie", "strang") or collision not in ("euler", "rk2"):
-            raise ValueError("scheme must be 'lie' or 'strang', collision 'euler' or 'rk2'")
+        if scheme not in ("lie", "strang") or collision not in ("euler", "rk2", "exp"):
+            raise ValueError("scheme must be 'lie' or 'strang', collision 'euler', 'rk2' or 'exp'")
+        if collision == "exp" and not (mu > 0 and math.isfinite(mu)):
+            raise ValueError("collision='exp' needs the penalization constant mu > 0")
+        self.mu = mu
         self.plan = plan
         self.space = space
         self.n = plan.n
@@ -74,7 +83,10 @@ class SplitStepper:
 
     def _collide(self, src, dst, dt_over_tau: float) -> None:
         nc = self.space.ncell
-        if self.collision == "euler":
+        if self.collision == "exp":
+            h = -math.expm1(-self.mu * dt_over_tau) / self.mu
+            collide_batch([(self.plan, src, None, dst, nc, h)], workspace=self.ws)
+        elif self.collision == "euler":
             collide_batch([(self.plan, src, None, dst, nc, dt_over_tau)], workspace=self.ws)
         else:
             collide_batch([(self.plan, src, None, self.mid, nc, 0.5 * dt_over_tau)], workspace=self.ws)

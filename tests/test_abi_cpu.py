@@ -176,3 +176,11 @@ def test_spectrum_workspace_size_host():
     assert fks.lib().fks_spectrum_workspace_size(1, 10, C.byref(b)) == fks.FKS_ERR_UNSUPPORTED
     assert fks.lib().fks_spectrum(None, None, 0, 16, 0, None, 0, None) == fks.FKS_OK      # empty batch
     assert fks.lib().fks_spectrum(None, None, 1, 16, 2, None, 0, None) == fks.FKS_ERR_INVALID
+
+
+def test_split_stepper_validates_its_options_before_touching_the_device():
+    from paper_1608_08009_amd.splitstep import SplitStepper
+    for kw in (dict(scheme="leapfrog"), dict(collision="rk4"), dict(collision="exp"),
+               dict(collision="exp", mu=float("inf"))):
+        with pytest.raises(ValueError):
+            SplitStepper(None, None, None, **kw)

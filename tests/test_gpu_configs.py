@@ -218,15 +218,19 @@ def test_f_base_stage_and_aliasing(prec, tol):
     assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("scheme,collision", [("strang", "euler"), ("lie", "rk2"), ("strang", "rk2")])
+@pytest.mark.parametrize("scheme,collision", [("strang", "euler"), ("lie", "rk2"), ("strang", "rk2"),
+                                              ("lie", "exp"), ("strang", "exp")])
 def test_split_step_variants_match_oracle(scheme, collision):
     n, T, nx, tau, steps = 16, 8.0, 8, 1e-2, 3
     f0, bc = _sod_initial(n, T, nx)
     plan = fks.Plan(fks.Desc(n=n, T=T, precision=fks.PREC_F64))
     space = Space(nx, 1, 1, 1.0 / nx, (fks.BC_DIRICHLET, fks.BC_PERIODIC, fks.BC_PERIODIC))
     dt = stable_dt(space, T, tau, plan.info.R, 1.0, plan.info.c_gamma, 1.0)
+    mu = 4.0 * math.pi * plan.info.c_gamma * 2.0 * plan.info.R     # loss-frequency bound at rho = 1
+    if collision == "exp":
+        dt *= 20.0                                                  # past the Euler limit tau / mu
     st = SplitStepper(plan, space, _dev(f0.reshape(1, 1, nx, n, n, n)), bc_f=_dev(bc),
-                      scheme=scheme, collision=collision)
+                      scheme=scheme, collision=collision, mu=mu)
     for _ in range(steps):
         st.step(dt, tau)
     torch.cuda.synchronize()
@@ -246,6 +250,8 @@ def test_split_step_variants_match_oracle(scheme, collision):
         for c in g.reshape(nx, n, n, n):
             if collision == "euler":
                 out.append(c + dt / tau * Qc(c))
+            elif collision == "exp":
+                out.append(O.exp_euler_update(c, Qc(c), dt / tau, mu))
             else:
                 out.append(c + dt / tau * Qc(c + 0.5 * dt / tau * Qc(c)))
         return np.stack(out).reshape(g.shape)
