@@ -7,9 +7,10 @@ fks_collide_batch over the whole batch: forward FFT, 32 gain terms and the
 loss term, FP64 conservation projection and the update f <- f + dt/tau Q_c
 (FP32 transforms and products, FP64 fix), inputs resident in HBM.
 
-Prints one JSON line (see the design notes for every field).  Also times the
-plain FP64 path and the CPU oracle on a bounded sample of the same cells,
-which doubles as a parity check of the timed configuration.
+Prints one JSON line: the throughput of the batch, the roofline of the dominant
+kernel, the CPU oracle on a bounded sample of the same cells (which doubles as a
+parity check of the timed configuration), the plain FP64 path, and the extra
+workloads (BGK, two velocity dimensions, de-aliased variant).
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cells·N³/s of Q(f,f) at N=32³, M=32 (FP32+fix vs FP64, rel err ≤1e-5)"
 UNIT = "cells·N³/s"
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X dense FP32 vector (packed) peak
-PEAK_FP32_UNPACKED_TFLOPS = 78.6    # without packed FP32 (disabled in this build): 256 CU x 64 lanes x 2 x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6    # without packed FP32 (the library is compiled with it off): 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X dense FP64 vector peak
 N_V, T_BOX, NCELL = 32, 8.0, 4096
 N_POLAR, N_AZIM = 8, 4
@@ -176,8 +177,9 @@ def main():
                     help="also run one 512 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(cells shard trivially across GPUs; see the design notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(cells are independent: a batch shards across GPUs by contiguous cell ranges with no "
+              "communication in the collision step). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -109,9 +109,11 @@ typedef struct {
     double  R;                 /* truncation radius actually used */
     double  c_gamma;           /* kernel constant actually used */
     int32_t precision;         /* fks_precision */
-    int32_t fused;             /* 1 if fks_collide_batch uses the single fused kernel */
+    int32_t fused;             /* 1 if fks_collide_batch uses the fused kernels (FP32, dim 3, n <= 32) */
     size_t  table_bytes;       /* device bytes held by the plan */
-    double  flops_per_cell;    /* algorithmic flop count of one Q evaluation (see design notes) */
+    double  flops_per_cell;    /* algorithmic flops of one Q evaluation: (2J'+2) 2.5 N log2 N + 7J' N + 3N,
+                                  N = n^3 (n^2 for dim 2), J' = J - 1 (a real FFT counts 2.5 N log2 N);
+                                  the de-aliased variant counts its zero-padded transforms instead */
     int32_t dim;               /* velocity dimension (2 or 3) */
     int32_t fused_grid;        /* workgroups the fused kernel keeps resident (0 if not fused) */
 } fks_plan_info;

@@ -3,7 +3,7 @@
 Only tests, the smoke check and the bench's CPU-baseline leg use this module.
 Nothing here is called by the HIP library, and nothing here calls it.
 
-Conventions (each is one reading of the paper, listed again in the design notes):
+Conventions (each is one reading of the paper):
 
 * Velocity grid (Section 3.1, eq. DM1): n points per axis on [-T, T), nodes
   v_j = -T + j dv, dv = 2T/n.  Arrays are indexed f[x][y][z] (C order).

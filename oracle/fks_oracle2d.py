@@ -2,7 +2,7 @@
 molecules (test infrastructure; only tests, the smoke check and the bench's
 CPU-baseline leg may use it, and it shares no code with the HIP library).
 
-Conventions (readings of the paper, listed again in the design notes):
+Conventions (readings of the paper):
 
 * Velocity grid and Fourier representation as in three dimensions
   (Section 3.1, eqs. FU and FC on [-T, T)^2): nodes v_j = -T + j dv,

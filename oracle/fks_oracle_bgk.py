@@ -7,7 +7,7 @@ moments of the cell and E[U] is the pointwise Maxwellian M[f] at the nodes
 (Section 2, eq. i5 and the temperature relation below it) projected back onto
 U with the minimisation of Section 3.2 (eq. minimMax), so that C E[U] = U.
 
-Readings (listed again in the design notes):
+Readings:
 * the temperature is d_v rho theta = sum |v|^2 f dv^{d_v} - rho |u|^2 (eq. i5's
   relation with E = (1/2) int |v|^2 f);
 * nu is either a constant (mu in Test 4.1) or nu = rho (Test 2.2), possibly scaled;

@@ -12,7 +12,7 @@ pairs with l + m = k exactly, for k in the band of the grid:
     Qhat_k = sum_{l, m in band, l + m = k} fhat_l fhat_m [B_F(l, m) - B_F(m, m)],
     band = {k : -n/2 < k_i < n/2}  (the Nyquist planes stay zero, as for fhat).
 
-Readings (listed again in the design notes):
+Readings:
 * Both factors of every product (a_j, b_j, and f_N with F^{-1}(L fhat)) are band
   limited to |k_i| <= n/2 - 1, so their product holds |k_i| <= n - 2.  Sampled
   on a grid of n' points per axis over the same box [-T, T), frequency p shows

@@ -1,6 +1,8 @@
 """GPU parity of the collision path (through the C ABI) against the CPU oracle.
 
-Bars (derived in the design notes):
+Bars (FP32 unit round-off is 6e-8; a few transform passes of log2(n^3) stages give
+errors of a few units relative to the gain and loss parts, which the cancellation
+between them amplifies in Q):
   * FP64 path: per-cell relative L2 of Q_c <= 1e-12 (hard spheres; K-term 1e-11);
   * FP32 + FP64-fix path: batch-aggregate relative L2 of Q_c <= 1e-5, and per
     cell <= 1.5e-6 * (1 + |Q-|/|Q_c|): FP32 roundoff of the transforms (a few
