@@ -190,10 +190,15 @@ fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* byt
 
 /*
  * Evaluates Q(f,f) for every cell of every segment (fast spectral form with
- * Nyquist planes zeroed), projects it onto the kernel of the collision
+ * Nyquist planes zeroed: the n-periodic convolution, or the de-aliased one for
+ * plans with FKS_FLAG_DEALIAS), projects it onto the kernel of the collision
  * invariants in FP64 and writes q_out / f_out.  workspace: device memory of at
- * least fks_workspace_size bytes, 256-byte aligned, owned by the caller, not
- * used concurrently by another call.  No device allocation happens inside.
+ * least fks_workspace_size bytes for the same segments (the size depends on
+ * ncell: large FP32 batches run one workgroup per cell, small ones pairs of
+ * workgroups with partial sums), 256-byte aligned, owned by the caller, not
+ * used concurrently by another call.  No device allocation, host
+ * synchronisation or memset happens inside, so the call can be captured in a
+ * HIP graph.  Results are deterministic (no floating-point atomics).
  * Errors: FKS_ERR_INVALID (NULL plan/f, both outputs NULL, ncell < 0,
  * misaligned arrays, small or misaligned workspace), FKS_ERR_DEVICE (launch
  * failure).
