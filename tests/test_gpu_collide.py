@@ -350,6 +350,38 @@ def test_one_workgroup_per_cell_numeric_guard():
         assert bool(torch.isfinite(q[good]).all())
 
 
+@pytest.mark.parametrize("n,gamma,K,prec,big", [
+    (16, 1.0, 0, fks.PREC_F32_FIX64, False),     # J = 2: one gain term and the loss term
+    (16, 1.0, 0, fks.PREC_F32_FIX64, True),      # same, two rounds of resident workgroups
+    (16, 0.5, 2, fks.PREC_F32_FIX64, False),     # J = 3
+    (8, 1.0, 0, fks.PREC_F64, False),
+])
+def test_single_direction_plans(n, gamma, K, prec, big):
+    # the smallest rule (one direction on the half sphere): degenerate term counts.  With so
+    # few terms a pair of workgroups per cell never pays for its second forward transform and
+    # finish kernel, so the fused path runs one workgroup per cell even for 5 cells
+    plan = _plan(n=n, T=T_BOX, gamma=gamma, radial_terms=K, n_polar=1, n_azim=1, precision=prec)
+    assert plan.info.M == 1 and plan.info.J == (K or 1) + 1
+    ncell = 2 * max(plan.info.fused_grid, 8) - 7 if big else 5
+    f = synth.two_maxwellian_torch(n, T_BOX, ncell, "cuda", seed_offset=250 + n)
+    q = torch.empty_like(f)
+    kernels = _kernels_of_last_call(lambda: fks.collide(plan, f, q_out=q))
+    if prec == fks.PREC_F32_FIX64:
+        assert kernels == 1
+    torch.cuda.synchronize()
+    sample = [0, ncell // 2, ncell - 1]
+    op = _oplan(n, T_BOX, gamma, 1, 1, K)
+    ref, ratio = _oracle_qc(f[sample].cpu().numpy(), op, ratios=True)
+    got = q[sample].cpu().numpy()
+    # per-cell cancellation-aware bars only: a one-direction rule has large gain and loss
+    # parts against a small Q (the aggregate bar is the metric workload's)
+    for i in range(len(sample)):
+        e = _rel(got[i], ref[i])
+        bar = max(1e-12, 3e-14 * (1.0 + ratio[i])) if prec == fks.PREC_F64 else 1.5e-6 * (1.0 + ratio[i])
+        assert e <= bar, (sample[i], e, ratio[i])
+    assert _conservation_torch(q, n, T_BOX) <= 1e-12
+
+
 # ---------------------------------------------------------------- full-size workload, sampled
 
 def test_full_size_hard_sphere_batch_sampled():
