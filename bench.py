@@ -364,6 +364,56 @@ def main():
             del wsd
         print(f"[bench] dealias: {msd:.2f} ms for {cd} cells", file=sys.stderr, flush=True)
 
+    # uneven batch: 2048 cells with (n, M, gamma) drawn from {16, 24, 32, 48} x {16, 32, 64} x
+    # {0, 0.5, 1}, one fks_collide_batch over 36 segments, FP32 + FP64 fix; timed with the built-in
+    # schedules, then after fks_autotune
+    uneven_line = None
+    if args.extras:
+        ns, Ms, gs = synth.uneven_batch_draws(2048)
+        groups = {}
+        for c in range(2048):
+            groups.setdefault((int(ns[c]), int(Ms[c]), float(gs[c])), []).append(c)
+        segs, plans_u, pts, flops = [], [], 0, 0.0
+        for gi, (key, cells) in enumerate(sorted(groups.items())):
+            nu_, mu_, gu_ = key
+            npol, naz = synth.UNEVEN_SPLIT[mu_]
+            pu = fks.Plan(fks.Desc(n=nu_, T=T_BOX, gamma=gu_, n_polar=npol, n_azim=naz,
+                                   precision=fks.PREC_F32_FIX64))
+            plans_u.append(pu)
+            fu = synth.two_maxwellian_torch(nu_, T_BOX, len(cells), dev, seed_offset=500 + gi)
+            segs.append((pu, fu, None, torch.empty_like(fu), len(cells), DT_OVER_TAU))
+            pts += len(cells) * nu_ ** 3
+            flops += len(cells) * pu.info.flops_per_cell
+
+        def time_uneven(reps=2):
+            wsu = torch.empty(max(fks.workspace_size(segs), 1), dtype=torch.uint8, device=dev)
+            fks.collide_batch(segs, workspace=wsu)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fks.collide_batch(segs, workspace=wsu)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_cost = time_uneven()
+        choices = fks.autotune(segs)
+        ms_tuned = time_uneven()
+        uneven_line = {"workload": "2048 cells, (n, M, gamma) from {16,24,32,48} x {16,32,64} x {0,0.5,1}, "
+                                   "36 segments in one call, FP32 + FP64 fix, f_out",
+                       "ms_cost_model": round(ms_cost, 3), "ms_autotuned": round(ms_tuned, 3),
+                       "value": pts / (ms_tuned * 1e-3), "unit": UNIT,
+                       "algorithmic_tflops": round(flops / (ms_tuned * 1e-3) / 1e12, 2),
+                       "schedules": {"fused_one_per_cell": sum(1 for o, c in choices if o == 1),
+                                     "fused_pairs": sum(1 for o, c in choices if o == 0),
+                                     "multi_pass_chunks": sorted({c for o, c in choices if c > 0})}}
+        for pu in plans_u:
+            pu.close()
+        del segs
+        print(f"[bench] uneven: {ms_cost:.2f} ms (cost model), {ms_tuned:.2f} ms (autotuned)",
+              file=sys.stderr, flush=True)
+
     # plain FP64 path (multi-pass), same workload
     fp64 = None
     if args.fp64_steps > 0:
@@ -445,6 +495,7 @@ def main():
         "bgk": bgk_line,
         "collide2d": d2_line,
         "dealias": dealias_line,
+        "uneven": uneven_line,
     }
     print(json.dumps(line), flush=True)
 

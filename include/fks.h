@@ -99,7 +99,8 @@ typedef struct {
  * (1, v_x, v_y, |v|^2), and fks_collide_batch needs no workspace for them.
  */
 
-typedef struct fks_plan fks_plan;   /* opaque: immutable after creation, owns device tables */
+typedef struct fks_plan fks_plan;   /* opaque: owns device tables; immutable after creation except
+                                       for the schedule cache that fks_autotune fills */
 
 typedef struct {
     int32_t n;                 /* as described */
@@ -205,6 +206,30 @@ fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* byt
  */
 fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace,
                              size_t ws_bytes, void* hip_stream);
+
+/*
+ * Autotuner.  For each segment, times the schedules fks_collide_batch can use
+ * for it and keeps the fastest in the segment's plan, keyed by ncell: for
+ * fused plans one workgroup per cell or pairs of workgroups per cell; for the
+ * multi-pass path (FP64, n = 48, FKS_FLAG_FORCE_GENERIC, FKS_FLAG_DEALIAS) the
+ * cells per pass batch (32, 64, 128, 256, 512 or ncell), which sets how much of
+ * the work arrays stays in the on-chip caches.  Later fks_workspace_size and
+ * fks_collide_batch calls with the same (plan, ncell) use the kept schedule;
+ * other sizes keep the built-in cost model.  Schedules change the summation
+ * order of the FP32 partial sums only, never the operator.
+ *   Each segment is evaluated several times (its outputs are overwritten): its
+ *   f_out must not overlap f or f_base.  workspace: at least
+ *   fks_autotune_workspace_size bytes for the same segments (candidates that do
+ *   not fit are skipped), 256-byte aligned.  choice_out: host [nseg][2] or
+ *   NULL, receives (one workgroup per cell 1 / pairs 0 / -1, cells per pass
+ *   batch or 0) per segment.  Synchronises hip_stream; not for graph capture;
+ *   no other call may use the same plans meanwhile.
+ * Errors: FKS_ERR_INVALID (as fks_collide_batch, or overlapping outputs),
+ * FKS_ERR_DEVICE.
+ */
+fks_status fks_autotune_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes);
+fks_status fks_autotune(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
+                        void* hip_stream, int32_t* choice_out);
 
 /*
  * Moments U = C f (eq. i5 on the grid, C of Section 3.2): for each cell

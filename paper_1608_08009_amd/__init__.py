@@ -41,7 +41,7 @@ EXPORTED = [
     "fks_transport_shift", "fks_status_string", "fks_desc_validate",
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
     "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
-    "fks_numeric_status",
+    "fks_numeric_status", "fks_autotune_workspace_size", "fks_autotune",
 ]
 
 
@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
     L.fks_spectrum_workspace_size.argtypes = [i64, i32, C.POINTER(sz)]
     L.fks_spectrum.argtypes = [vp, vp, i64, i32, i32, vp, sz, vp]
     L.fks_numeric_status.argtypes = [vp, C.POINTER(i64), i32]
+    L.fks_autotune_workspace_size.argtypes = [C.POINTER(Segment), i32, C.POINTER(sz)]
+    L.fks_autotune.argtypes = [C.POINTER(Segment), i32, vp, sz, vp, vp]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -311,6 +313,31 @@ def collide_batch(segments, workspace=None, stream=None):
     _check(lib().fks_collide_batch(arr, len(segments), C.c_void_p(_ptr(workspace)), workspace.numel(),
                                    C.c_void_p(_stream_ptr(stream))), "fks_collide_batch")
     return workspace
+
+
+def autotune(segments, workspace=None, stream=None):
+    """fks_autotune: times the schedules of every segment and keeps the fastest in its plan
+    (for the same ncell).  The segments are evaluated several times, so their f_out must not
+    overlap f or f_base.  Returns [(one, chunk)] per segment: one = 1 (one workgroup per
+    cell), 0 (pairs) or -1 (not a fused plan); chunk = cells per pass batch of the
+    multi-pass path, or 0."""
+    import torch
+    for item in segments:
+        plan, f, q_out, f_out, ncell, dt, f_base = _segment_fields(item)
+        nn = ncell * plan.cell_size
+        _require_device_f64(f, "f", nn)
+        _require_device_f64(q_out, "q_out", nn)
+        _require_device_f64(f_out, "f_out", nn)
+        _require_device_f64(f_base, "f_base", nn)
+    arr = _segments(segments)
+    if workspace is None:
+        need = C.c_size_t()
+        _check(lib().fks_autotune_workspace_size(arr, len(segments), C.byref(need)), "fks_autotune_workspace_size")
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device="cuda")
+    choice = (C.c_int32 * (2 * max(len(segments), 1)))()
+    _check(lib().fks_autotune(arr, len(segments), C.c_void_p(_ptr(workspace)), workspace.numel(),
+                              C.c_void_p(_stream_ptr(stream)), choice), "fks_autotune")
+    return [(int(choice[2 * i]), int(choice[2 * i + 1])) for i in range(len(segments))]
 
 
 def collide(plan: Plan, f, q_out=None, f_out=None, dt_over_tau: float = 0.0, workspace=None, stream=None,

@@ -594,6 +594,132 @@ fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* worksp
     return FKS_OK;
 }
 
+// Candidate schedules of one segment: the two fused decompositions, or cells per
+// pass batch of the multi-pass path.  Empty when nothing is to be chosen.
+static std::vector<Schedule> schedule_candidates(const fks_segment& s) {
+    std::vector<Schedule> c;
+    if (s.ncell <= 0 || s.plan->dim == 2) return c;
+    if (s.plan->fused) {
+        c.push_back(Schedule{1, 0});
+        c.push_back(Schedule{0, 0});
+        return c;
+    }
+    for (int chunk : {32, 64, 128, 256, 512}) {
+        if (chunk >= s.ncell) {
+            c.push_back(Schedule{-1, (int)s.ncell});
+            break;
+        }
+        c.push_back(Schedule{-1, chunk});
+    }
+    return c;
+}
+
+// sets (or with erase, removes) the measured schedule of (plan, ncell)
+static void set_schedule(fks_plan* p, int64_t ncell, const Schedule* sc) {
+    for (size_t i = 0; i < p->tuned.size(); ++i) {
+        if (p->tuned[i].first == ncell) {
+            if (sc) p->tuned[i].second = *sc;
+            else p->tuned.erase(p->tuned.begin() + i);
+            return;
+        }
+    }
+    if (sc) p->tuned.emplace_back(ncell, *sc);
+}
+
+static hipError_t collide_one(const fks_segment& g, void* ws, size_t ws_bytes, hipStream_t s) {
+    return g.plan->fused ? collide_fused(g.plan, g, ws, ws_bytes, s) : collide_generic(g.plan, g, ws, ws_bytes, s);
+}
+
+fks_status fks_autotune_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes) {
+    if (!bytes || nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
+    size_t mx = 0;
+    for (int i = 0; i < nseg; ++i) {
+        fks_status st = check_segment(segs[i]);
+        if (st != FKS_OK) return st;
+        fks_plan* p = const_cast<fks_plan*>(segs[i].plan);
+        const auto saved = p->tuned;
+        for (const Schedule& c : schedule_candidates(segs[i])) {
+            set_schedule(p, segs[i].ncell, &c);
+            mx = std::max(mx, segment_ws(segs[i]));
+        }
+        p->tuned = saved;
+        mx = std::max(mx, segment_ws(segs[i]));
+    }
+    *bytes = mx;
+    return FKS_OK;
+}
+
+fks_status fks_autotune(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes, void* hip_stream,
+                        int32_t* choice_out) {
+    if (nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
+    if (workspace && ((uintptr_t)workspace & 255u)) return FKS_ERR_INVALID;
+    for (int i = 0; i < nseg; ++i) {
+        const fks_segment& g = segs[i];
+        fks_status st = check_segment(g);
+        if (st != FKS_OK) return st;
+        // the segment is evaluated several times: its outputs must not feed its inputs
+        const size_t bytes = (size_t)g.ncell * g.plan->desc.n * g.plan->desc.n * (g.plan->dim == 2 ? 1 : g.plan->desc.n) *
+                             sizeof(double);
+        const double* in[2] = {g.f, g.f_base ? g.f_base : g.f};
+        for (const double* a : in) {
+            if (g.f_out && (const char*)a < (const char*)g.f_out + bytes && (const char*)g.f_out < (const char*)a + bytes)
+                return FKS_ERR_INVALID;
+        }
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t ev[2];
+    if (hipEventCreate(&ev[0]) != hipSuccess) return FKS_ERR_DEVICE;
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return FKS_ERR_DEVICE;
+    }
+    fks_status result = FKS_OK;
+    for (int i = 0; i < nseg && result == FKS_OK; ++i) {
+        const fks_segment& g = segs[i];
+        fks_plan* p = const_cast<fks_plan*>(g.plan);
+        if (choice_out) {
+            choice_out[2 * i] = -1;
+            choice_out[2 * i + 1] = 0;
+        }
+        const std::vector<Schedule> cand = schedule_candidates(g);
+        if (cand.empty()) continue;
+        set_schedule(p, g.ncell, nullptr);
+        int best = -1;
+        float best_ms = 0.0f;
+        for (size_t k = 0; k < cand.size(); ++k) {
+            set_schedule(p, g.ncell, &cand[k]);
+            const size_t need = segment_ws(g);
+            if (need > ws_bytes || (need > 0 && !workspace)) continue;
+            float ms = 0.0f;
+            if (collide_one(g, workspace, ws_bytes, s) != hipSuccess ||            // warm-up
+                hipEventRecord(ev[0], s) != hipSuccess ||
+                collide_one(g, workspace, ws_bytes, s) != hipSuccess ||
+                collide_one(g, workspace, ws_bytes, s) != hipSuccess ||
+                hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+                result = FKS_ERR_DEVICE;
+                break;
+            }
+            if (best < 0 || ms < best_ms) {
+                best = (int)k;
+                best_ms = ms;
+            }
+        }
+        if (best < 0 || result != FKS_OK) {
+            set_schedule(p, g.ncell, nullptr);   // nothing fitted the workspace: keep the defaults
+            continue;
+        }
+        set_schedule(p, g.ncell, &cand[best]);
+        if (choice_out) {
+            choice_out[2 * i] = cand[best].one;
+            choice_out[2 * i + 1] = cand[best].chunk;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return result;
+}
+
 fks_status fks_moments(const double* f, int64_t ncell, int32_t n, double T, double* U, void* hip_stream) {
     if (ncell < 0 || !(T > 0) || !std::isfinite(T) || n < 2 || n > 64) return FKS_ERR_INVALID;
     if (ncell == 0) return FKS_OK;

@@ -557,6 +557,8 @@ inline int npairs_for(const fks_plan* p, int64_t ncell) {
 // transform and no partial sums in HBM).
 inline bool one_per_cell(const fks_plan* p, int64_t ncell) {
     if (ncell <= 0) return false;
+    const Schedule sc = schedule_for(p, ncell);   // measured by fks_autotune
+    if (sc.one >= 0) return sc.one == 1;
     const int64_t G = p->fused_grid;
     const int64_t J = p->J;
     const int64_t c1 = (ncell + G - 1) / G * (J + 1);

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "../../include/fks.h"
@@ -32,6 +33,13 @@ struct ShiftTable {
     int8_t s[3][64];
 };
 
+// Schedule of one (plan, ncell): fused path one workgroup per cell (1) or pairs (0),
+// -1 = the cost model; multi-pass path cells per pass batch, 0 = the default.
+struct Schedule {
+    int one = -1;
+    int chunk = 0;
+};
+
 }  // namespace fks
 
 struct fks_plan {
@@ -54,9 +62,17 @@ struct fks_plan {
     int fused_grid = 0;             // persistent grid of the fused kernel
     double flops_per_cell = 0.0;
     int device = 0;
+    std::vector<std::pair<int64_t, fks::Schedule>> tuned;   // measured by fks_autotune, per ncell
 };
 
 namespace fks {
+
+// the measured schedule of (plan, ncell), or the default Schedule{} if none
+inline Schedule schedule_for(const fks_plan* p, int64_t ncell) {
+    for (const auto& e : p->tuned)
+        if (e.first == ncell) return e.second;
+    return Schedule{};
+}
 
 // host math (fks_abi.hip)
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
