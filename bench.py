@@ -405,9 +405,10 @@ def main():
                        "ms_cost_model": round(ms_cost, 3), "ms_autotuned": round(ms_tuned, 3),
                        "value": pts / (ms_tuned * 1e-3), "unit": UNIT,
                        "algorithmic_tflops": round(flops / (ms_tuned * 1e-3) / 1e12, 2),
-                       "schedules": {"fused_one_per_cell": sum(1 for o, c in choices if o == 1),
-                                     "fused_pairs": sum(1 for o, c in choices if o == 0),
-                                     "multi_pass_chunks": sorted({c for o, c in choices if c > 0})}}
+                       "schedules": {"fused_one_per_cell": sum(1 for o, c, t in choices if o == 1),
+                                     "fused_pairs": sum(1 for o, c, t in choices if o == 0),
+                                     "multi_pass_chunks": sorted({c for o, c, t in choices if c > 0}),
+                                     "multi_pass_terms_per_launch": sorted({t for o, c, t in choices if t > 0})}}
         for pu in plans_u:
             pu.close()
         del segs

@@ -213,16 +213,18 @@ fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* worksp
  * fused plans one workgroup per cell or pairs of workgroups per cell; for the
  * multi-pass path (FP64, n = 48, FKS_FLAG_FORCE_GENERIC, FKS_FLAG_DEALIAS) the
  * cells per pass batch (32, 64, 128, 256, 512 or ncell), which sets how much of
- * the work arrays stays in the on-chip caches.  Later fks_workspace_size and
+ * the work arrays stays in the on-chip caches, and the consecutive terms per
+ * launch of the per-term kernels (1, 2 or 4; not for FKS_FLAG_DEALIAS), which
+ * trades launches and accumulator traffic for work-array space.  Later fks_workspace_size and
  * fks_collide_batch calls with the same (plan, ncell) use the kept schedule;
  * other sizes keep the built-in cost model.  Schedules change the summation
  * order of the FP32 partial sums only, never the operator.
  *   Each segment is evaluated several times (its outputs are overwritten): its
  *   f_out must not overlap f or f_base.  workspace: at least
  *   fks_autotune_workspace_size bytes for the same segments (candidates that do
- *   not fit are skipped), 256-byte aligned.  choice_out: host [nseg][2] or
+ *   not fit are skipped), 256-byte aligned.  choice_out: host [nseg][3] or
  *   NULL, receives (one workgroup per cell 1 / pairs 0 / -1, cells per pass
- *   batch or 0) per segment.  Synchronises hip_stream; not for graph capture;
+ *   batch or 0, terms per launch or 0) per segment.  Synchronises hip_stream; not for graph capture;
  *   no other call may use the same plans meanwhile.
  * Errors: FKS_ERR_INVALID (as fks_collide_batch, or overlapping outputs),
  * FKS_ERR_DEVICE.

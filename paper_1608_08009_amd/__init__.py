@@ -318,9 +318,9 @@ def collide_batch(segments, workspace=None, stream=None):
 def autotune(segments, workspace=None, stream=None):
     """fks_autotune: times the schedules of every segment and keeps the fastest in its plan
     (for the same ncell).  The segments are evaluated several times, so their f_out must not
-    overlap f or f_base.  Returns [(one, chunk)] per segment: one = 1 (one workgroup per
-    cell), 0 (pairs) or -1 (not a fused plan); chunk = cells per pass batch of the
-    multi-pass path, or 0."""
+    overlap f or f_base.  Returns [(one, chunk, terms)] per segment: one = 1 (one workgroup
+    per cell), 0 (pairs) or -1 (not a fused plan); chunk = cells per pass batch and terms =
+    consecutive terms per launch of the multi-pass path, or 0."""
     import torch
     for item in segments:
         plan, f, q_out, f_out, ncell, dt, f_base = _segment_fields(item)
@@ -334,10 +334,10 @@ def autotune(segments, workspace=None, stream=None):
         need = C.c_size_t()
         _check(lib().fks_autotune_workspace_size(arr, len(segments), C.byref(need)), "fks_autotune_workspace_size")
         workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device="cuda")
-    choice = (C.c_int32 * (2 * max(len(segments), 1)))()
+    choice = (C.c_int32 * (3 * max(len(segments), 1)))()
     _check(lib().fks_autotune(arr, len(segments), C.c_void_p(_ptr(workspace)), workspace.numel(),
                               C.c_void_p(_stream_ptr(stream)), choice), "fks_autotune")
-    return [(int(choice[2 * i]), int(choice[2 * i + 1])) for i in range(len(segments))]
+    return [tuple(int(choice[3 * i + k]) for k in range(3)) for i in range(len(segments))]
 
 
 def collide(plan: Plan, f, q_out=None, f_out=None, dt_over_tau: float = 0.0, workspace=None, stream=None,

@@ -604,12 +604,15 @@ static std::vector<Schedule> schedule_candidates(const fks_segment& s) {
         c.push_back(Schedule{0, 0});
         return c;
     }
+    // the de-aliased variant and FP64 at n = 48 have no terms-per-launch knob
+    const bool multi = generic_multi_terms(s.plan);
     for (int chunk : {32, 64, 128, 256, 512}) {
-        if (chunk >= s.ncell) {
-            c.push_back(Schedule{-1, (int)s.ncell});
-            break;
+        const int ch = chunk >= s.ncell ? (int)s.ncell : chunk;
+        for (int terms : {1, 2, 4}) {
+            if (!multi && terms > 1) break;
+            c.push_back(Schedule{-1, ch, multi ? terms : 0});
         }
-        c.push_back(Schedule{-1, chunk});
+        if (chunk >= s.ncell) break;
     }
     return c;
 }
@@ -678,8 +681,9 @@ fks_status fks_autotune(const fks_segment* segs, int32_t nseg, void* workspace, 
         const fks_segment& g = segs[i];
         fks_plan* p = const_cast<fks_plan*>(g.plan);
         if (choice_out) {
-            choice_out[2 * i] = -1;
-            choice_out[2 * i + 1] = 0;
+            choice_out[3 * i] = -1;
+            choice_out[3 * i + 1] = 0;
+            choice_out[3 * i + 2] = 0;
         }
         const std::vector<Schedule> cand = schedule_candidates(g);
         if (cand.empty()) continue;
@@ -711,8 +715,9 @@ fks_status fks_autotune(const fks_segment* segs, int32_t nseg, void* workspace, 
         }
         set_schedule(p, g.ncell, &cand[best]);
         if (choice_out) {
-            choice_out[2 * i] = cand[best].one;
-            choice_out[2 * i + 1] = cand[best].chunk;
+            choice_out[3 * i] = cand[best].one;
+            choice_out[3 * i + 1] = cand[best].chunk;
+            choice_out[3 * i + 2] = cand[best].terms;
         }
     }
     (void)hipEventDestroy(ev[0]);

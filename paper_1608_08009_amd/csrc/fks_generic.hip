@@ -17,19 +17,36 @@
 #include "fks_common.hpp"
 
 namespace fks {
+
+bool generic_multi_terms(const fks_plan* p) {
+    return !(p->desc.precision == FKS_PREC_F64 && p->desc.n >= 48) && !(p->desc.flags & FKS_FLAG_DEALIAS);
+}
+
 namespace {
 
-constexpr int kChunk = 512;          // cells per pass batch (spectrum; n < 32)
-constexpr int kChunkLarge = 128;     // cells per pass batch for n >= 32 and the de-aliased path
+constexpr int kChunk = 512;          // cells per pass batch
+constexpr int kChunkOneTerm = 128;   // cells per pass batch where each launch takes one term (n >= 32)
+constexpr int kTermsPerLaunch = 4;   // consecutive terms per launch of the per-term kernels
 
-// cells per pass batch: the measured choice of fks_autotune, else the default.  For
-// n >= 32 smaller batches keep more of the work arrays in the on-chip caches: 4096 cells
-// of 32^3 in FP64 take 64 ms with 128-cell batches against 76 ms with 512, and 1024 cells
-// of 48^3 in FP32 32 ms against 35 ms; at n = 16 the autotuner keeps 512.
+// consecutive terms per launch of the per-term kernels: the measured choice of
+// fks_autotune, else the default (one where the loop does not fit the registers)
+inline int terms_per_launch(const fks_plan* p, int64_t ncell) {
+    if (!generic_multi_terms(p)) return 1;
+    const Schedule sc = schedule_for(p, ncell);
+    return sc.terms > 0 ? sc.terms : kTermsPerLaunch;
+}
+
+// cells per pass batch: the measured choice of fks_autotune, else the default.  With four
+// terms per launch, 512-cell batches were the fastest measured (4096 cells of 32^3 in FP64:
+// 61.6 ms; 1024 cells of 48^3 in FP32: 29.7 ms).  Where each launch takes one term (the
+// de-aliased variant, FP64 at n = 48) smaller batches keep more of the work arrays in the
+// caches (4096 cells of 32^3 in FP64, one term per launch: 64 ms with 128 cells against
+// 76 ms with 512).
 inline int chunk_cells(const fks_plan* p, int64_t ncell) {
     const Schedule sc = schedule_for(p, ncell);
     if (sc.chunk > 0) return sc.chunk;
-    return ((p->desc.flags & FKS_FLAG_DEALIAS) || p->desc.n >= 32) ? kChunkLarge : kChunk;
+    if ((p->desc.flags & FKS_FLAG_DEALIAS) || (!generic_multi_terms(p) && p->desc.n >= 32)) return kChunkOneTerm;
+    return kChunk;
 }
 
 template <typename T>
@@ -123,10 +140,23 @@ __device__ __forceinline__ void plane_sync() {
     }
 }
 
+// hides a pointer from loop-invariant code motion (the loads through it stay in the loop)
+template <typename P>
+__device__ __forceinline__ P hide(P p) {
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
+// several terms per launch only where the loop state fits the registers (FP64 at n = 48
+// already uses all 256 VGPRs for the transform)
 template <typename T, int N>
+constexpr bool multi_term_ok() { return !(sizeof(T) == 8 && N >= 48); }
+
+template <typename T, int N, bool MT>
 __global__ __launch_bounds__(zy_planes<N>() * N) void g_inv_zy(const cx<T>* __restrict__ fh,
-                                                               const cx<T>* __restrict__ tab,
-                                                               cx<T>* __restrict__ work, int C) {
+                                                               const cx<T>* __restrict__ tab0,
+                                                               cx<T>* __restrict__ work0, int C, int nt,
+                                                               int64_t work_stride) {
     constexpr int PP = zy_planes<N>();
     constexpr int RS = N + 1;
     __shared__ T lds[PP * N * RS];
@@ -138,17 +168,30 @@ __global__ __launch_bounds__(zy_planes<N>() * N) void g_inv_zy(const cx<T>* __re
     const int ky = i;
     const int mx = (N - kx) % N, my = (N - ky) % N;
     constexpr int H = (N / 2 + 1) * N * N;
-    const cx<T>* g = fh + c * H;
+    const cx<T>* const g0 = fh + c * H;
+    const int nterm = MT ? nt : 1;
+#pragma nounroll
+    for (int t = 0; t < nterm; ++t) {   // nt consecutive terms, one work array each
+    const cx<T>* const tab = tab0 + (size_t)t * H;
+    cx<T>* const work = work0 + t * work_stride;
+    // For n > 16, fhat is reloaded and the offsets recomputed every term (cache hits, a few
+    // integer ops) rather than hoisted out of the loop into registers, which would cost the
+    // kernel its occupancy; for n <= 16 the registers are there and the hoisting pays
+    // (8192 cells of 16^3 in FP64: 12.1 -> 7.8 ms)
+    constexpr bool keep = N <= 16;
+    const cx<T>* const g = keep ? g0 : hide(g0);
+    const int kxh = keep ? kx : hide(kx), kyh = keep ? ky : hide(ky);
+    const int mxh = keep ? mx : hide(mx), myh = keep ? my : hide(my);
     cx<T> v[N];
     sfor<N>([&](auto I) {
         constexpr int kz = decltype(I)::value;
         cx<T> a, b;
         if constexpr (kz <= N / 2) {
-            const int h = (kz * N + kx) * N + ky;
+            const int h = (kz * N + kxh) * N + kyh;
             a = tab[h];
             b = g[h];
         } else {
-            const int h = ((N - kz) * N + mx) * N + my;   // fhat(-k) = conj fhat(k); tables even in k
+            const int h = ((N - kz) * N + mxh) * N + myh;   // fhat(-k) = conj fhat(k); tables even in k
             a = tab[h];
             b = g[h];
             b.y = -b.y;
@@ -166,28 +209,36 @@ __global__ __launch_bounds__(zy_planes<N>() * N) void g_inv_zy(const cx<T>* __re
     plane_sync<T, N>();
     sfor<N>([&](auto I) { u[decltype(I)::value].y = blk[decltype(I)::value * RS + i]; });
     fft<T, N, 1>(u);   // over ky: column z = i, registers over y
-    if (!live) return;
-    cx<T>* o = work + (c * N + kx) * N * N + i;
-    sfor<N>([&](auto I) {
-        constexpr int y = decltype(I)::value;
-        o[y * N] = u[y];
-    });
+    if (live) {
+        cx<T>* o = work + (c * N + kx) * N * N + i;
+        sfor<N>([&](auto I) {
+            constexpr int y = decltype(I)::value;
+            o[y * N] = u[y];
+        });
+    }
+    plane_sync<T, N>();   // the next term reuses the LDS block
+    }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work, T* __restrict__ acc, int C,
-                                               int first) {
+template <typename T, int N, bool MT>
+__global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work0, T* __restrict__ acc, int C,
+                                               int first0, int nt, int64_t work_stride) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= C * N * N) return;
     const int z = t % N, y = (t / N) % N, c = t / (N * N);
-    const cx<T>* p = work + (size_t)c * N * N * N + y * N + z;
+    // nt consecutive terms: the accumulator lines stay in the caches between them
+    const int nterm = MT ? nt : 1;
+#pragma nounroll
+    for (int term = 0; term < nterm; ++term) {
+    const int first = first0 && term == 0;
+    const cx<T>* p = hide(work0 + term * work_stride + (size_t)c * N * N * N + y * N + z);
     cx<T> v[N];
     sfor<N>([&](auto I) {
         constexpr int k = decltype(I)::value;
         v[k] = p[k * N * N];
     });
     fft<T, N, 1>(v);
-    T* q = acc + (size_t)c * N * N * N + y * N + z;
+    T* q = hide(acc + (size_t)c * N * N * N + y * N + z);
     // accumulator read-modify-write in groups of x, fenced so that the compiler does not
     // load every accumulator at once (which costs the FP64 kernel half its occupancy)
     constexpr int G = (N % 8 == 0) ? 8 : N;
@@ -204,6 +255,7 @@ __global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work, T
         });
         __builtin_amdgcn_sched_barrier(0);
     });
+    }
 }
 
 template <typename T, int N>
@@ -508,10 +560,12 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
     constexpr int H = (N / 2 + 1) * N * N;
     constexpr size_t NN = (size_t)N * N * N;
     const int chunk = (int)std::min<int64_t>(s.ncell, chunk_cells(p, s.ncell));
+    const int TB = terms_per_launch(p, s.ncell);
     char* base = (char*)ws;
     cx<T>* fh = (cx<T>*)base;
     cx<T>* work = (cx<T>*)(base + align256((size_t)chunk * H * sizeof(cx<T>)));
-    T* acc = (T*)((char*)work + align256((size_t)chunk * NN * sizeof(cx<T>)));
+    const int64_t work_stride = (int64_t)(align256((size_t)chunk * NN * sizeof(cx<T>)) / sizeof(cx<T>));
+    T* acc = (T*)(work + TB * work_stride);
     const cx<T>* tab = Tab<T>::get(p);
     const int bs = 128;
     for (int64_t c0 = 0; c0 < s.ncell; c0 += chunk) {
@@ -523,9 +577,15 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
         g_fwd_z<T, N><<<grid, bs, 0, st>>>(work, fh, C);
         constexpr int PP = zy_planes<N>();
         const unsigned gzy = (unsigned)(((int64_t)C * N + PP - 1) / PP);
-        for (int j = 0; j < p->J; ++j) {
-            g_inv_zy<T, N><<<gzy, PP * N, 0, st>>>(fh, tab + (size_t)j * H, work, C);
-            g_inv_x<T, N><<<grid, bs, 0, st>>>(work, acc, C, j == 0 ? 1 : 0);
+        for (int j = 0; j < p->J; j += TB) {
+            const int nt = std::min(TB, p->J - j);
+            if constexpr (multi_term_ok<T, N>()) {
+                g_inv_zy<T, N, true><<<gzy, PP * N, 0, st>>>(fh, tab + (size_t)j * H, work, C, nt, work_stride);
+                g_inv_x<T, N, true><<<grid, bs, 0, st>>>(work, acc, C, j == 0 ? 1 : 0, nt, work_stride);
+            } else {
+                g_inv_zy<T, N, false><<<gzy, PP * N, 0, st>>>(fh, tab + (size_t)j * H, work, C, 1, work_stride);
+                g_inv_x<T, N, false><<<grid, bs, 0, st>>>(work, acc, C, j == 0 ? 1 : 0, 1, work_stride);
+            }
         }
         const double* fb = (s.f_base ? s.f_base : s.f) + c0 * (int64_t)NN;
         g_finish<T, N><<<C, 256, 0, st>>>(acc, fb, s.q_out ? s.q_out + c0 * (int64_t)NN : nullptr,
@@ -631,11 +691,12 @@ size_t generic_workspace_bytes(const fks_plan* p, int64_t ncell) {
                                                  : dealias_layout<float>(n, 3 * n / 2, chunk).total;
     }
     const int chunk = (int)std::min<int64_t>(ncell, chunk_cells(p, ncell));
+    const size_t TB = (size_t)terms_per_launch(p, ncell);
     size_t H = (size_t)(n / 2 + 1) * n * n, NN = (size_t)n * n * n;
     if (p->desc.precision == FKS_PREC_F64)
-        return align256(chunk * H * sizeof(cx<double>)) + align256(chunk * NN * sizeof(cx<double>)) +
+        return align256(chunk * H * sizeof(cx<double>)) + TB * align256(chunk * NN * sizeof(cx<double>)) +
                align256(chunk * NN * sizeof(double));
-    return align256(chunk * H * sizeof(cx<float>)) + align256(chunk * NN * sizeof(cx<float>)) +
+    return align256(chunk * H * sizeof(cx<float>)) + TB * align256(chunk * NN * sizeof(cx<float>)) +
            align256(chunk * NN * sizeof(float));
 }
 

@@ -38,6 +38,7 @@ struct ShiftTable {
 struct Schedule {
     int one = -1;
     int chunk = 0;
+    int terms = 0;   // multi-pass path: consecutive terms per launch, 0 = the default
 };
 
 }  // namespace fks
@@ -85,6 +86,7 @@ hipError_t build_tables(fks_plan* plan, hipStream_t stream);
 
 // multi-pass path, FP64 and FP32 (fks_generic.hip)
 size_t generic_workspace_bytes(const fks_plan* plan, int64_t ncell);
+bool generic_multi_terms(const fks_plan* plan);   // several terms per launch available
 hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
                            hipStream_t stream);
 

@@ -1,7 +1,8 @@
 """The autotuner (fks_autotune): it keeps, per (plan, ncell), the fastest of the schedules
 fks_collide_batch can use; later calls follow the kept schedule; schedules never change the
-operator (multi-pass chunking is bit-identical, the fused decompositions agree to FP32
-round-off); segments whose outputs feed their inputs are rejected."""
+operator (multi-pass chunking and terms per launch are bit-identical, the fused
+decompositions agree to FP32 round-off); segments whose outputs feed their inputs are
+rejected."""
 import pytest
 
 import synth
@@ -31,8 +32,8 @@ def test_fused_choice_is_kept_and_followed():
         q, q64 = torch.empty_like(f), torch.empty_like(f)
         fks.collide(p64, f, q_out=q64)
         seg = [(plan, f, q, None, ncell, 0.0)]
-        (one, chunk), = fks.autotune(seg)
-        assert one in (0, 1) and chunk == 0
+        (one, chunk, terms), = fks.autotune(seg)
+        assert one in (0, 1) and chunk == 0 and terms == 0
         ws = torch.empty(max(fks.workspace_size(seg), 1), dtype=torch.uint8, device="cuda")
         assert _kernels(lambda: fks.collide_batch(seg, workspace=ws)) == (1 if one else 2)
         torch.cuda.synchronize()
@@ -53,8 +54,9 @@ def test_multi_pass_chunking_is_bit_identical(n, prec, flags):
         q0, q1 = torch.empty_like(f), torch.empty_like(f)
         fks.collide(plan, f, q_out=q0)
         seg = [(plan, f, q1, None, ncell, 0.0)]
-        (one, chunk), = fks.autotune(seg)
+        (one, chunk, terms), = fks.autotune(seg)
         assert one == -1 and chunk in (32, 64, 100)
+        assert terms == (0 if flags & fks.FLAG_DEALIAS else terms) and terms in (0, 1, 2, 4)
         q1.fill_(0.0)
         fks.collide_batch(seg)
         torch.cuda.synchronize()
@@ -72,8 +74,8 @@ def test_rejections_and_tight_workspace_and_2d():
         seg = [(plan, f, q, None, ncell, 0.0)]
         # a workspace for the default schedule only: the larger candidates are skipped
         ws = torch.empty(fks.workspace_size(seg), dtype=torch.uint8, device="cuda")
-        (one, chunk), = fks.autotune(seg, workspace=ws)
-        assert one == -1 and chunk in (32, 40)
+        (one, chunk, terms), = fks.autotune(seg, workspace=ws)
+        assert one == -1 and chunk in (32, 40) and terms in (1, 2, 4)
     with fks.Plan(fks.desc2d(16, 6.0, 8, fks.PREC_F64)) as p2:
         g = torch.as_tensor(synth.two_maxwellian_cells_2d(16, 6.0, 4, seed_offset=281), device="cuda")
-        assert fks.autotune([(p2, g, torch.empty_like(g), None, 4, 0.0)]) == [(-1, 0)]
+        assert fks.autotune([(p2, g, torch.empty_like(g), None, 4, 0.0)]) == [(-1, 0, 0)]
