@@ -121,11 +121,19 @@ __device__ __forceinline__ void cell_sync() {
     }
 }
 
+// LDS slot of a cell's block: 8 bytes, a complex value in FP32, a real value in FP64 (whose
+// complex exchanges go through the block in two rounds, real parts then imaginary parts,
+// which halves the block and doubles the cells a CU holds)
+template <typename R>
+struct Slot { using type = cx<float>; };
+template <>
+struct Slot<double> { using type = double; };
+
 // cells per workgroup: n threads each, at most 256 threads and 128 KiB of LDS
 template <typename R, int N>
 constexpr int cells_per_block() {
     constexpr int by_threads = 256 / N;
-    constexpr int by_lds = (128 * 1024) / (N * (N + 1) * (int)sizeof(cx<R>));
+    constexpr int by_lds = (128 * 1024) / (N * (N + 1) * (int)sizeof(typename Slot<R>::type));
     constexpr int c = by_threads < by_lds ? by_threads : by_lds;
     return c < 1 ? 1 : c;
 }
@@ -148,13 +156,33 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
     constexpr int CPB = cells_per_block<R, N>();
     constexpr int RS = N + 1;
     constexpr int NN = N * N;
-    __shared__ cx<R> lds[CPB * N * RS];
-    static_assert(N * 4 * sizeof(double) <= N * RS * sizeof(cx<R>), "reduction buffer inside a cell's block");
+    using E = typename Slot<R>::type;
+    static_assert(sizeof(E) == sizeof(double), "8-byte LDS slots");
+    __shared__ E lds[CPB * N * RS];
+    static_assert(N * 4 * sizeof(double) <= N * RS * sizeof(E), "reduction buffer inside a cell's block");
     const int t = threadIdx.x;
     const int c = t / N, i = t % N;
     const int64_t cell = (int64_t)blockIdx.x * CPB + c;
     const bool live = cell < A.ncell;
-    cx<R>* const blk = lds + c * N * RS;
+    E* const blk = lds + c * N * RS;
+    // row layout -> column layout of one cell: src[k] of thread i lands in dst[i] of thread k
+    auto transpose = [&](cx<R>(&src)[N], cx<R>(&dst)[N]) {
+        if constexpr (sizeof(R) == 4) {
+            sfor<N>([&](auto kI) { blk[decltype(kI)::value * RS + i] = src[decltype(kI)::value]; });
+            cell_sync<N>();
+            sfor<N>([&](auto kI) { dst[decltype(kI)::value] = blk[i * RS + decltype(kI)::value]; });
+            cell_sync<N>();
+        } else {
+            sfor<N>([&](auto kI) { blk[decltype(kI)::value * RS + i] = src[decltype(kI)::value].x; });
+            cell_sync<N>();
+            sfor<N>([&](auto kI) { dst[decltype(kI)::value].x = blk[i * RS + decltype(kI)::value]; });
+            cell_sync<N>();
+            sfor<N>([&](auto kI) { blk[decltype(kI)::value * RS + i] = src[decltype(kI)::value].y; });
+            cell_sync<N>();
+            sfor<N>([&](auto kI) { dst[decltype(kI)::value].y = blk[i * RS + decltype(kI)::value]; });
+            cell_sync<N>();
+        }
+    };
     const cx<R>* const tab = (const cx<R>*)A.tab;
 
     // ---- forward transform: row x = i over y, then columns over x ----
@@ -165,27 +193,21 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         const double* fc = A.f + (live ? cell : 0) * (int64_t)NN + i;
         sfor<N>([&](auto xI) {
             constexpr int x = decltype(xI)::value;
-            blk[x * RS + i] = cx<R>{live ? (R)fc[x * N] : R(0), R(0)};
+            const R v = live ? (R)fc[x * N] : R(0);
+            if constexpr (sizeof(R) == 4) blk[x * RS + i] = cx<float>{v, 0.0f};
+            else blk[x * RS + i] = v;
         });
         cell_sync<N>();
         sfor<N>([&](auto yI) {
             constexpr int y = decltype(yI)::value;
-            z[y] = blk[i * RS + y];
+            if constexpr (sizeof(R) == 4) z[y] = blk[i * RS + y];
+            else z[y] = cx<R>{blk[i * RS + y], R(0)};
         });
         cell_sync<N>();
     }
     fft<R, N, -1>(z);
-    sfor<N>([&](auto kI) {   // row layout -> column layout: blk[ky][x]
-        constexpr int k = decltype(kI)::value;
-        blk[k * RS + i] = z[k];
-    });
-    cell_sync<N>();
     cx<R> fh[N];   // column ky = i, registers over kx
-    sfor<N>([&](auto kI) {
-        constexpr int k = decltype(kI)::value;
-        fh[k] = blk[i * RS + k];
-    });
-    cell_sync<N>();
+    transpose(z, fh);
     fft<R, N, -1>(fh);
     {
         const R s = (i == N / 2) ? R(0) : R(1) / R(NN);
@@ -221,16 +243,7 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
             __builtin_amdgcn_sched_barrier(0);
         });
         fft<R, N, 1>(z);   // over kx: column ky = i, registers over x
-        sfor<N>([&](auto xI) {
-            constexpr int x = decltype(xI)::value;
-            blk[x * RS + i] = z[x];
-        });
-        cell_sync<N>();
-        sfor<N>([&](auto kI) {
-            constexpr int k = decltype(kI)::value;
-            z[k] = blk[i * RS + k];
-        });
-        cell_sync<N>();
+        transpose(z, z);
         fft<R, N, 1>(z);   // over ky: row x = i, registers over y
         sfor<N>([&](auto yI) {
             constexpr int y = decltype(yI)::value;
@@ -273,7 +286,7 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         atomicMin(A.guard, (unsigned long long)cell);
     // Q_c of row x = i into the block (one double per slot), then coalesced stores: lane i
     // writes element y = i of every row
-    constexpr int W = sizeof(cx<R>) / sizeof(double);
+    constexpr int W = 1;   // one double per 8-byte slot
     double* const bd = (double*)blk;
     cell_sync<N>();   // every thread has read the partial sums
     const double lx = fma(lam[1], ux, lam[0]);
