@@ -76,6 +76,17 @@ def _oracle_extra_worker(args):
         step = lambda g: g + DT_OVER_TAU * O.conserve_Q(O.fks_oracle_dealias.collide_dealias_fast64(g, op),  # noqa: E731
                                                         N_V, T_BOX)
         pts = N_V ** 3
+    elif kind == "halo":
+        # the whole-grid transport of the oracle (what the slabs reproduce) on a 2 x 2 x 4 grid of
+        # 24^3 velocities, periodic, the bench's CFL; one step is one sample
+        import numpy as np
+        hn, hT = 24, 8.0
+        dx = 0.5
+        g0 = synth.rng(96).uniform(size=(4, 2, 2, hn, hn, hn))
+        _, sh = O.transport_offsets_step(np.zeros((3, hn)), hn, hT, dx, 0.95 * dx / hT)
+        f = [g0] * 64
+        step = lambda g: O.transport_shift(g, sh, hn)  # noqa: E731
+        pts = g0.size
     else:
         raise ValueError(kind)
     count, t0 = 0, time.perf_counter()
@@ -93,9 +104,10 @@ def cpu_extras(kinds):
     out = {}
     for kind, count, pts, t in res:
         unit = "cells·N²/s" if kind == "collide2d" else UNIT
+        what = (f"{count} whole-grid transport steps of a 2x2x4 grid of 24^3 velocities (the oracle's "
+                "element loop)" if kind == "halo" else f"{count} cells of the same workload")
         out[kind] = {"value": count * pts / t, "unit": unit, "cores": 1, "kind": "oracle",
-                     "sample": f"{count} cells of the same workload, numpy FP64, one single-threaded "
-                               f"process ({t:.1f} s)"}
+                     "sample": f"{what}, numpy FP64, one single-threaded process ({t:.1f} s)"}
     return out
 
 
@@ -296,6 +308,66 @@ def main():
                                  "frac": round(alg / (ms_bgk * 1e-3) / 8e12, 4), "bytes_per_launch": alg}}
         print(f"[bench] bgk: {ms_bgk:.3f} ms per batch", file=sys.stderr, flush=True)
 
+    # z-slab transport with halo exchange: one GPU's share of the 32^3-cell, 24^3-velocity flow on
+    # eight GPUs (4 owned planes of 32 x 32 cells).  Per step: pack the two outgoing messages,
+    # unpack two incoming ones into the ghost planes (here the slab's own, a ring of one), then
+    # the slab transport.  Moving the messages between GPUs is not part of this one-GPU figure.
+    halo_line = None
+    if args.extras:
+        hn, hT, hx, hy, hz = 24, 8.0, 32, 32, 4
+        hdx = 1.0 / hx
+        hdt = 0.95 * hdx / hT
+        g = torch.Generator(device="cuda").manual_seed(1608080096)
+        ext_a = torch.rand(((hz + 2), hy, hx, hn ** 3), dtype=torch.float64, device="cuda", generator=g)
+        ext_b = torch.empty_like(ext_a)
+        msgs = {f: torch.empty(fks.halo_size(hx, hy, hz, hn, f) // 8, dtype=torch.float64, device="cuda")
+                for f in (fks.FACE_ZLO, fks.FACE_ZHI)}
+        off = np.zeros((3, hn))
+        periodic = (fks.BC_PERIODIC, fks.BC_PERIODIC)
+
+        def halo_exchange(ext):
+            for f in (fks.FACE_ZLO, fks.FACE_ZHI):
+                fks.halo_pack(ext, msgs[f], hx, hy, hz, hn, f)
+            for f in (fks.FACE_ZLO, fks.FACE_ZHI):
+                fks.halo_unpack(ext, msgs[f], hx, hy, hz, hn, f)
+
+        for _ in range(2):
+            halo_exchange(ext_a)
+            fks.transport_shift_slab(ext_a, ext_b, hx, hy, hz, hdx, periodic, hn, hT, hdt, off)
+            ext_a, ext_b = ext_b, ext_a
+        torch.cuda.synchronize()
+        reps = 10
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * reps)]
+        for r in range(reps):
+            ev[3 * r].record(stream)
+            halo_exchange(ext_a)
+            ev[3 * r + 1].record(stream)
+            fks.transport_shift_slab(ext_a, ext_b, hx, hy, hz, hdx, periodic, hn, hT, hdt, off)
+            ev[3 * r + 2].record(stream)
+            ext_a, ext_b = ext_b, ext_a
+        torch.cuda.synchronize()
+        ms_x = sum(ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(reps)) / reps
+        ms_t = sum(ev[3 * r + 1].elapsed_time(ev[3 * r + 2]) for r in range(reps)) / reps
+        msg_bytes = sum(m.numel() * 8 for m in msgs.values())
+        x_bytes = 4.0 * msg_bytes                       # pack: read + write, unpack: read + write
+        t_bytes = hz * hy * hx * hn ** 3 * 16.0          # slab transport: read f, write f_out
+        pts = hz * hy * hx * hn ** 3
+        halo_line = {"workload": f"one GPU's share of a {hx}x{hy}x{8 * hz} grid on 8 GPUs: {hz} planes of "
+                                 f"{hx}x{hy} cells, {hn}^3 velocities, periodic, CFL 0.95",
+                     "ms": round(ms_x + ms_t, 4), "ms_halo_pack_unpack": round(ms_x, 4),
+                     "ms_slab_transport": round(ms_t, 4), "message_bytes_per_face": msg_bytes // 2,
+                     "value": pts / ((ms_x + ms_t) * 1e-3), "unit": UNIT,
+                     "roofline": {"bound": "hbm", "achieved": round(x_bytes / (ms_x * 1e-3) / 1e9, 1),
+                                  "peak": 8000.0, "unit": "GB/s",
+                                  "frac": round(x_bytes / (ms_x * 1e-3) / 8e12, 4), "bytes_per_launch": x_bytes,
+                                  "kernels": "halo pack + unpack, both faces"},
+                     "transport_roofline": {"bound": "hbm", "achieved": round(t_bytes / (ms_t * 1e-3) / 1e9, 1),
+                                            "peak": 8000.0, "unit": "GB/s",
+                                            "frac": round(t_bytes / (ms_t * 1e-3) / 8e12, 4)}}
+        del ext_a, ext_b, msgs
+        print(f"[bench] halo: {ms_x:.3f} ms pack+unpack, {ms_t:.3f} ms slab transport", file=sys.stderr,
+              flush=True)
+
     # two velocity dimensions: Maxwell molecules, 8192 cells of 32^2, A = 8 (Test 1.1 resolution)
     d2_line = None
     if args.extras:
@@ -454,13 +526,15 @@ def main():
 
     # the oracle beside the extra lines (bounded samples, one core each)
     if args.extras and args.cpu_sample > 0:
-        extra_cpu = cpu_extras(["collide2d", "bgk", "dealias"])
+        extra_cpu = cpu_extras(["collide2d", "bgk", "dealias", "halo"])
         if d2_line is not None:
             d2_line["cpu_baseline"] = extra_cpu["collide2d"]
         if bgk_line is not None:
             bgk_line["cpu_baseline"] = extra_cpu["bgk"]
         if dealias_line is not None:
             dealias_line["cpu_baseline"] = extra_cpu["dealias"]
+        if halo_line is not None:
+            halo_line["cpu_baseline"] = extra_cpu["halo"]
 
     line = {
         "metric": METRIC,
@@ -496,6 +570,7 @@ def main():
         "bgk": bgk_line,
         "collide2d": d2_line,
         "dealias": dealias_line,
+        "halo": halo_line,
         "uneven": uneven_line,
     }
     print(json.dumps(line), flush=True)

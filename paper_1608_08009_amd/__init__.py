@@ -34,6 +34,8 @@ BGK_EULER = 0
 BGK_EXACT = 1
 BC_PERIODIC = 0
 BC_DIRICHLET = 1
+FACE_ZLO = 0
+FACE_ZHI = 1
 
 EXPORTED = [
     "fks_plan_create", "fks_plan_destroy", "fks_plan_query", "fks_plan_copy_tables",
@@ -42,6 +44,7 @@ EXPORTED = [
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
     "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
     "fks_numeric_status", "fks_autotune_workspace_size", "fks_autotune",
+    "fks_halo_size", "fks_halo_pack", "fks_halo_unpack", "fks_transport_shift_slab",
 ]
 
 
@@ -119,6 +122,10 @@ def lib() -> C.CDLL:
     L.fks_numeric_status.argtypes = [vp, C.POINTER(i64), i32]
     L.fks_autotune_workspace_size.argtypes = [C.POINTER(Segment), i32, C.POINTER(sz)]
     L.fks_autotune.argtypes = [C.POINTER(Segment), i32, vp, sz, vp, vp]
+    L.fks_halo_size.argtypes = [C.POINTER(SpaceDesc), i32, i32, C.POINTER(sz)]
+    L.fks_halo_pack.argtypes = [vp, C.POINTER(SpaceDesc), i32, i32, vp, vp]
+    L.fks_halo_unpack.argtypes = [vp, C.POINTER(SpaceDesc), i32, i32, vp, vp]
+    L.fks_transport_shift_slab.argtypes = [vp, vp, C.POINTER(SpaceDesc), i32, dbl, dbl, vp, vp, vp]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -387,6 +394,53 @@ def transport_shift(f_in, f_out, nx: int, ny: int, nz: int, dx: float, bc, n: in
     _check(lib().fks_transport_shift(C.c_void_p(_ptr(f_in)), C.c_void_p(_ptr(f_out)), C.byref(sp), n, T, dt,
                                      C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(bc_f)),
                                      C.c_void_p(_stream_ptr(stream))), "fks_transport_shift")
+
+
+def halo_size(nx: int, ny: int, nz: int, n: int, face: int) -> int:
+    """Bytes of the message that leaves a z slab of nz owned planes through `face`."""
+    sp = SpaceDesc(nx, ny, nz, 1.0, (C.c_int32 * 3)(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC))
+    out = C.c_size_t(0)
+    _check(lib().fks_halo_size(C.byref(sp), n, face, C.byref(out)), "fks_halo_size")
+    return out.value
+
+
+def _slab_args(f_ext, buf, nx, ny, nz, n, face):
+    _require_device_f64(f_ext, "f_ext", (nz + 2) * nx * ny * n ** 3)
+    _require_device_f64(buf, "buf", halo_size(nx, ny, nz, n, face) // 8)
+    return SpaceDesc(nx, ny, nz, 1.0, (C.c_int32 * 3)(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC))
+
+
+def halo_pack(f_ext, buf, nx: int, ny: int, nz: int, n: int, face: int, stream=None):
+    """Packs the velocities leaving the slab f_ext [nz + 2, ny, nx, n^3] through `face` into buf."""
+    sp = _slab_args(f_ext, buf, nx, ny, nz, n, face)
+    _check(lib().fks_halo_pack(C.c_void_p(_ptr(f_ext)), C.byref(sp), n, face, C.c_void_p(_ptr(buf)),
+                               C.c_void_p(_stream_ptr(stream))), "fks_halo_pack")
+
+
+def halo_unpack(f_ext, buf, nx: int, ny: int, nz: int, n: int, face: int, stream=None):
+    """Unpacks a message that left the neighbouring slab through `face` into the ghost plane it enters."""
+    sp = _slab_args(f_ext, buf, nx, ny, nz, n, face)
+    _check(lib().fks_halo_unpack(C.c_void_p(_ptr(f_ext)), C.byref(sp), n, face, C.c_void_p(_ptr(buf)),
+                                 C.c_void_p(_stream_ptr(stream))), "fks_halo_unpack")
+
+
+def transport_shift_slab(f_ext_in, f_ext_out, nx: int, ny: int, nz: int, dx: float, bc_xy, n: int, T: float,
+                         dt: float, offsets, bc_f=None, stream=None):
+    """Transport step of a z slab with filled ghost planes: owned planes of f_ext_in -> f_ext_out
+    (both [nz + 2, ny, nx, n^3]); offsets as in transport_shift (updated)."""
+    import numpy as np
+    total = (nz + 2) * nx * ny * n ** 3
+    _require_device_f64(f_ext_in, "f_ext_in", total)
+    _require_device_f64(f_ext_out, "f_ext_out", total)
+    if bc_f is not None:
+        _require_device_f64(bc_f, "bc_f", 6 * n ** 3)
+    if not (isinstance(offsets, np.ndarray) and offsets.dtype == np.float64 and offsets.size == 3 * n
+            and offsets.flags.c_contiguous):
+        raise ValueError("offsets must be a contiguous float64 numpy array of 3*n values")
+    sp = SpaceDesc(nx, ny, nz, dx, (C.c_int32 * 3)(bc_xy[0], bc_xy[1], BC_PERIODIC))
+    _check(lib().fks_transport_shift_slab(C.c_void_p(_ptr(f_ext_in)), C.c_void_p(_ptr(f_ext_out)), C.byref(sp),
+                                          n, T, dt, C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(bc_f)),
+                                          C.c_void_p(_stream_ptr(stream))), "fks_transport_shift_slab")
 
 
 def bgk(f, n: int, T: float, nu: float, dim: int = 3, q_out=None, f_out=None, dt_over_tau: float = 0.0,

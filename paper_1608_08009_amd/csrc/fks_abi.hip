@@ -617,6 +617,71 @@ static std::vector<Schedule> schedule_candidates(const fks_segment& s) {
     return c;
 }
 
+// Transport step shared by the whole-grid and the slab entry points: validation, the
+// per-axis displacement update and integer shifts (host, FP64), then the shift kernel.
+// A slab reads its z neighbours from the ghost planes, so its z shift must be -1, 0 or 1.
+static fks_status transport_step(const double* f_in, double* f_out, const fks_space_desc* sp, int32_t n, double T,
+                                 double dt, double* offsets, const double* bc_f, void* hip_stream, bool slab) {
+    if (!f_in || !f_out || !sp || !offsets) return FKS_ERR_INVALID;
+    if (n < 2 || n > 64 || !(T > 0) || !std::isfinite(T) || !std::isfinite(dt)) return FKS_ERR_INVALID;
+    if (sp->nx < 1 || sp->ny < 1 || sp->nz < 1 || !(sp->dx > 0) || !std::isfinite(sp->dx)) return FKS_ERR_INVALID;
+    bool any_dirichlet = false;
+    for (int a = 0; a < (slab ? 2 : 3); ++a) {
+        if (sp->bc[a] != FKS_BC_PERIODIC && sp->bc[a] != FKS_BC_DIRICHLET) return FKS_ERR_INVALID;
+        any_dirichlet |= sp->bc[a] == FKS_BC_DIRICHLET;
+    }
+    if (any_dirichlet && !bc_f) return FKS_ERR_INVALID;
+    const size_t plane = (size_t)sp->nx * sp->ny * n * n * n * sizeof(double);
+    const size_t bytes = plane * (sp->nz + (slab ? 2 : 0));
+    const char* a = (const char*)f_in;
+    const char* b = (const char*)f_out;
+    if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
+    ShiftTable sh{};
+    const double dv = 2.0 * T / n;
+    double next[3][64];
+    for (int ax = 0; ax < 3; ++ax)
+        for (int k = 0; k < n; ++k) {
+            double v = -T + k * dv;
+            double s0 = offsets[ax * n + k];
+            double s1 = s0 + v * dt;
+            if (!std::isfinite(s1)) return FKS_ERR_INVALID;
+            double d0 = std::floor(s0 / sp->dx + 0.5), d1 = std::floor(s1 / sp->dx + 0.5);
+            double dd = d1 - d0;
+            if (dd > 127 || dd < -127) return FKS_ERR_INVALID;
+            // a slab's ghost planes hold only what crosses its faces: a z shift of +1 is
+            // allowed for the velocities sent up (v_z > 0), -1 for those sent down (v_z < 0)
+            if (slab && ax == 2 && dd != 0 && !(dd == 1 && 2 * k > n) && !(dd == -1 && 2 * k < n))
+                return FKS_ERR_INVALID;
+            sh.s[ax][k] = (int8_t)dd;
+            next[ax][k] = s1;
+        }
+    const size_t skip = slab ? plane / sizeof(double) : 0;   // the first owned plane
+    hipError_t e = transport(f_in + skip, f_out + skip, *sp, n, sh, bc_f, (hipStream_t)hip_stream, slab);
+    if (e != hipSuccess) return FKS_ERR_DEVICE;
+    for (int ax = 0; ax < 3; ++ax)
+        for (int k = 0; k < n; ++k) offsets[ax * n + k] = next[ax][k];
+    return FKS_OK;
+}
+
+static bool slab_valid(const fks_space_desc* sp, int32_t n) {
+    return sp && n >= 2 && n <= 64 && sp->nx >= 1 && sp->ny >= 1 && sp->nz >= 1;
+}
+
+// Velocities that leave a slab through a z face: v_z < 0 (kz < n/2) through z-, v_z > 0
+// (kz > n/2) through z+; v_z = 0 never crosses.  Their kz form one range [k0, k0 + h).
+static bool halo_range(int32_t n, int32_t face, int* k0, int* h) {
+    if (face == FKS_FACE_ZLO) {
+        *k0 = 0;
+        *h = (n + 1) / 2;
+    } else if (face == FKS_FACE_ZHI) {
+        *k0 = n / 2 + 1;
+        *h = n - 1 - n / 2;
+    } else {
+        return false;
+    }
+    return true;
+}
+
 // sets (or with erase, removes) the measured schedule of (plan, ncell)
 static void set_schedule(fks_plan* p, int64_t ncell, const Schedule* sc) {
     for (size_t i = 0; i < p->tuned.size(); ++i) {
@@ -791,40 +856,43 @@ fks_status fks_bgk(const fks_bgk_desc* d, const double* f, double* q_out, double
 
 fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_space_desc* sp, int32_t n,
                                double T, double dt, double* offsets, const double* bc_f, void* hip_stream) {
-    if (!f_in || !f_out || !sp || !offsets) return FKS_ERR_INVALID;
-    if (n < 2 || n > 64 || !(T > 0) || !std::isfinite(T) || !std::isfinite(dt)) return FKS_ERR_INVALID;
-    if (sp->nx < 1 || sp->ny < 1 || sp->nz < 1 || !(sp->dx > 0) || !std::isfinite(sp->dx)) return FKS_ERR_INVALID;
-    bool any_dirichlet = false;
-    for (int a = 0; a < 3; ++a) {
-        if (sp->bc[a] != FKS_BC_PERIODIC && sp->bc[a] != FKS_BC_DIRICHLET) return FKS_ERR_INVALID;
-        any_dirichlet |= sp->bc[a] == FKS_BC_DIRICHLET;
-    }
-    if (any_dirichlet && !bc_f) return FKS_ERR_INVALID;
-    size_t bytes = (size_t)sp->nx * sp->ny * sp->nz * n * n * n * sizeof(double);
-    const char* a = (const char*)f_in;
-    const char* b = (const char*)f_out;
-    if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
-    // per-axis displacement update and integer shifts (host, FP64)
-    ShiftTable sh{};
-    const double dv = 2.0 * T / n;
-    double next[3][64];
-    for (int ax = 0; ax < 3; ++ax)
-        for (int k = 0; k < n; ++k) {
-            double v = -T + k * dv;
-            double s0 = offsets[ax * n + k];
-            double s1 = s0 + v * dt;
-            if (!std::isfinite(s1)) return FKS_ERR_INVALID;
-            double d0 = std::floor(s0 / sp->dx + 0.5), d1 = std::floor(s1 / sp->dx + 0.5);
-            double dd = d1 - d0;
-            if (dd > 127 || dd < -127) return FKS_ERR_INVALID;
-            sh.s[ax][k] = (int8_t)dd;
-            next[ax][k] = s1;
-        }
-    hipError_t e = transport(f_in, f_out, *sp, n, sh, bc_f, (hipStream_t)hip_stream);
-    if (e != hipSuccess) return FKS_ERR_DEVICE;
-    for (int ax = 0; ax < 3; ++ax)
-        for (int k = 0; k < n; ++k) offsets[ax * n + k] = next[ax][k];
+    return transport_step(f_in, f_out, sp, n, T, dt, offsets, bc_f, hip_stream, false);
+}
+
+fks_status fks_transport_shift_slab(const double* f_ext_in, double* f_ext_out, const fks_space_desc* slab,
+                                    int32_t n, double T, double dt, double* offsets, const double* bc_f,
+                                    void* hip_stream) {
+    return transport_step(f_ext_in, f_ext_out, slab, n, T, dt, offsets, bc_f, hip_stream, true);
+}
+
+fks_status fks_halo_size(const fks_space_desc* slab, int32_t n, int32_t face, size_t* bytes) {
+    if (!bytes) return FKS_ERR_INVALID;
+    int k0 = 0, h = 0;
+    if (!slab_valid(slab, n) || !halo_range(n, face, &k0, &h)) return FKS_ERR_INVALID;
+    *bytes = (size_t)slab->nx * slab->ny * n * n * h * sizeof(double);
     return FKS_OK;
+}
+
+fks_status fks_halo_pack(const double* f_ext, const fks_space_desc* slab, int32_t n, int32_t face, double* buf,
+                         void* hip_stream) {
+    int k0 = 0, h = 0;
+    if (!f_ext || !buf || !slab_valid(slab, n) || !halo_range(n, face, &k0, &h)) return FKS_ERR_INVALID;
+    // the outgoing velocities of the first (z-) or last (z+) owned plane
+    const int64_t plane = face == FKS_FACE_ZLO ? 1 : slab->nz;
+    hipError_t e = halo_copy(const_cast<double*>(f_ext), buf, plane, (int64_t)slab->nx * slab->ny, n, k0, h, true,
+                             (hipStream_t)hip_stream);
+    return e == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
+}
+
+fks_status fks_halo_unpack(double* f_ext, const fks_space_desc* slab, int32_t n, int32_t face, const double* buf,
+                           void* hip_stream) {
+    int k0 = 0, h = 0;
+    // a message that left a neighbour through `face` enters this slab through the opposite face
+    if (!f_ext || !buf || !slab_valid(slab, n) || !halo_range(n, face, &k0, &h)) return FKS_ERR_INVALID;
+    const int64_t ghost = face == FKS_FACE_ZHI ? 0 : slab->nz + 1;
+    hipError_t e = halo_copy(f_ext, const_cast<double*>(buf), ghost, (int64_t)slab->nx * slab->ny, n, k0, h, false,
+                             (hipStream_t)hip_stream);
+    return e == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
 }
 
 }  // extern "C"

@@ -184,3 +184,27 @@ def test_split_stepper_validates_its_options_before_touching_the_device():
                dict(collision="exp", mu=float("inf"))):
         with pytest.raises(ValueError):
             SplitStepper(None, None, None, **kw)
+
+
+def test_halo_sizes_and_rejections_on_the_host():
+    # message sizes of the z-slab exchange: ceil(n/2) values of kz leave through z-, n - 1 - floor(n/2) through z+
+    for n, lo, hi in ((4, 2, 1), (5, 3, 2), (24, 12, 11)):
+        assert fks.halo_size(3, 2, 5, n, fks.FACE_ZLO) == 3 * 2 * n * n * lo * 8
+        assert fks.halo_size(3, 2, 5, n, fks.FACE_ZHI) == 3 * 2 * n * n * hi * 8
+    for args in ((3, 2, 5, 4, 2), (3, 2, 5, 1, 0), (3, 2, 0, 4, 0), (0, 2, 5, 4, 1)):
+        with pytest.raises(fks.FksError):
+            fks.halo_size(*args)
+    L = fks.lib()
+    sp = fks.SpaceDesc(3, 2, 5, 0.25, (C.c_int32 * 3)(0, 0, 0))
+    fake_a, fake_b = C.c_void_p(1 << 20), C.c_void_p(1 << 40)   # never dereferenced: rejected first
+    assert L.fks_halo_pack(None, C.byref(sp), 4, 0, fake_b, None) == fks.FKS_ERR_INVALID
+    assert L.fks_halo_pack(fake_a, C.byref(sp), 4, 3, fake_b, None) == fks.FKS_ERR_INVALID
+    assert L.fks_halo_unpack(fake_a, C.byref(sp), 4, 1, None, None) == fks.FKS_ERR_INVALID
+    assert L.fks_halo_unpack(fake_a, None, 4, 1, fake_b, None) == fks.FKS_ERR_INVALID
+    # a slab step whose z shift exceeds what the ghost planes hold is refused, offsets untouched
+    n, T = 4, 2.0
+    off = np.zeros((3, n))
+    for dt in (2.2 * 0.25 / T, -0.5 * 0.25 / T):
+        assert L.fks_transport_shift_slab(fake_a, fake_b, C.byref(sp), n, T, dt, C.c_void_p(off.ctypes.data),
+                                          None, None) == fks.FKS_ERR_INVALID
+        assert not off.any()
