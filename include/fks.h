@@ -286,9 +286,8 @@ fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_spac
  * messages between GPUs (point-to-point send/receive) is the caller's.
  *
  * A slab owns slab->nz consecutive z planes of a grid of slab->nx x slab->ny
- * cells, stored with one ghost plane on each side:
- *   f_ext  device [slab->nz + 2][ny][nx][n^3] FP64; plane 0 is the ghost below
- *          the slab, planes 1..nz are owned, plane nz + 1 is the ghost above.
+ * cells:
+ *   f      device [slab->nz][ny][nx][n^3] FP64 (no ghost planes).
  * Under CFL <= 1 the only masses that cross a z face in one step are those of
  * the velocities moving through it: v_z < 0 (kz < n/2, ceil(n/2) values of kz)
  * leave through z-, v_z > 0 (kz > n/2, n - 1 - floor(n/2) values) through z+.
@@ -304,34 +303,26 @@ fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_spac
 fks_status fks_halo_size(const fks_space_desc* slab, int32_t n, int32_t face, size_t* bytes);
 
 /* Packs the message that leaves through `face`: the outgoing velocities of the
- * first (FKS_FACE_ZLO) or last (FKS_FACE_ZHI) owned plane of f_ext into buf.
- * f_ext is only read.  Enqueued on hip_stream.  Errors: FKS_ERR_INVALID,
- * FKS_ERR_DEVICE. */
-fks_status fks_halo_pack(const double* f_ext, const fks_space_desc* slab, int32_t n, int32_t face,
+ * first (FKS_FACE_ZLO) or last (FKS_FACE_ZHI) plane of f into buf.  f is only
+ * read.  Enqueued on hip_stream.  Errors: FKS_ERR_INVALID, FKS_ERR_DEVICE. */
+fks_status fks_halo_pack(const double* f, const fks_space_desc* slab, int32_t n, int32_t face,
                          double* buf, void* hip_stream);
 
-/* Unpacks a message that left the neighbouring slab through `face` into the
- * ghost plane it enters: FKS_FACE_ZHI (the neighbour below sent it up) fills
- * ghost plane 0, FKS_FACE_ZLO (the neighbour above sent it down) fills ghost
- * plane nz + 1.  Only the velocities of the message are written; the rest of
- * the ghost plane is left as it is (the slab transport never reads it).
- * Enqueued on hip_stream.  Errors: FKS_ERR_INVALID, FKS_ERR_DEVICE. */
-fks_status fks_halo_unpack(double* f_ext, const fks_space_desc* slab, int32_t n, int32_t face,
-                           const double* buf, void* hip_stream);
-
-/* fks_transport_shift on a slab whose ghost planes hold the neighbours'
- * messages: writes owned planes 1..nz of f_ext_out (ghost planes untouched),
- * reading owned and ghost planes of f_ext_in.  x and y take slab->bc[0..1] as
- * in fks_transport_shift; slab->bc[2] is not read.  offsets, dt and bc_f as in
- * fks_transport_shift; every slab of a grid advances the same offsets.
- * Periodic z across the whole grid is the neighbours' wiring (the top slab's
- * z+ neighbour is the bottom slab).  The z shift of the step must stay within
- * what the ghosts hold: +1 only for v_z > 0, -1 only for v_z < 0 (CFL <= 1,
- * dt >= 0), else FKS_ERR_INVALID before anything is enqueued and offsets
- * unchanged.  f_ext_in and f_ext_out must not overlap.
- * Errors: FKS_ERR_INVALID, FKS_ERR_DEVICE. */
-fks_status fks_transport_shift_slab(const double* f_ext_in, double* f_ext_out, const fks_space_desc* slab,
+/* fks_transport_shift on a slab, f_in -> f_out (both [nz][ny][nx][n^3]), where
+ * what enters through the z faces comes from the neighbours' messages:
+ *   from_below  device, the message the slab below packed at its FKS_FACE_ZHI;
+ *   from_above  device, the message the slab above packed at its FKS_FACE_ZLO
+ * (for a periodic z axis the bottom slab's neighbour below is the top slab; a
+ * single slab may pass its own messages).  x and y take slab->bc[0..1] as in
+ * fks_transport_shift; slab->bc[2] is not read.  offsets, dt and bc_f as in
+ * fks_transport_shift; every slab of a grid advances the same offsets.  The z
+ * shift of the step must stay within what the messages hold: +1 only for
+ * v_z > 0, -1 only for v_z < 0 (CFL <= 1, dt >= 0), else FKS_ERR_INVALID before
+ * anything is enqueued and offsets unchanged.  f_in and f_out must not overlap;
+ * the messages must not overlap f_out.  Errors: FKS_ERR_INVALID, FKS_ERR_DEVICE. */
+fks_status fks_transport_shift_slab(const double* f_in, double* f_out, const fks_space_desc* slab,
                                     int32_t n, double T, double dt, double* offsets,
+                                    const double* from_below, const double* from_above,
                                     const double* bc_f, void* hip_stream);
 
 /*

@@ -44,7 +44,7 @@ EXPORTED = [
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
     "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
     "fks_numeric_status", "fks_autotune_workspace_size", "fks_autotune",
-    "fks_halo_size", "fks_halo_pack", "fks_halo_unpack", "fks_transport_shift_slab",
+    "fks_halo_size", "fks_halo_pack", "fks_transport_shift_slab",
 ]
 
 
@@ -124,8 +124,7 @@ def lib() -> C.CDLL:
     L.fks_autotune.argtypes = [C.POINTER(Segment), i32, vp, sz, vp, vp]
     L.fks_halo_size.argtypes = [C.POINTER(SpaceDesc), i32, i32, C.POINTER(sz)]
     L.fks_halo_pack.argtypes = [vp, C.POINTER(SpaceDesc), i32, i32, vp, vp]
-    L.fks_halo_unpack.argtypes = [vp, C.POINTER(SpaceDesc), i32, i32, vp, vp]
-    L.fks_transport_shift_slab.argtypes = [vp, vp, C.POINTER(SpaceDesc), i32, dbl, dbl, vp, vp, vp]
+    L.fks_transport_shift_slab.argtypes = [vp, vp, C.POINTER(SpaceDesc), i32, dbl, dbl, vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name != "fks_status_string":
             getattr(L, name).restype = C.c_int
@@ -404,42 +403,35 @@ def halo_size(nx: int, ny: int, nz: int, n: int, face: int) -> int:
     return out.value
 
 
-def _slab_args(f_ext, buf, nx, ny, nz, n, face):
-    _require_device_f64(f_ext, "f_ext", (nz + 2) * nx * ny * n ** 3)
+def halo_pack(f, buf, nx: int, ny: int, nz: int, n: int, face: int, stream=None):
+    """Packs the velocities leaving the slab f [nz, ny, nx, n^3] through `face` into buf."""
+    _require_device_f64(f, "f", nz * nx * ny * n ** 3)
     _require_device_f64(buf, "buf", halo_size(nx, ny, nz, n, face) // 8)
-    return SpaceDesc(nx, ny, nz, 1.0, (C.c_int32 * 3)(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC))
-
-
-def halo_pack(f_ext, buf, nx: int, ny: int, nz: int, n: int, face: int, stream=None):
-    """Packs the velocities leaving the slab f_ext [nz + 2, ny, nx, n^3] through `face` into buf."""
-    sp = _slab_args(f_ext, buf, nx, ny, nz, n, face)
-    _check(lib().fks_halo_pack(C.c_void_p(_ptr(f_ext)), C.byref(sp), n, face, C.c_void_p(_ptr(buf)),
+    sp = SpaceDesc(nx, ny, nz, 1.0, (C.c_int32 * 3)(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC))
+    _check(lib().fks_halo_pack(C.c_void_p(_ptr(f)), C.byref(sp), n, face, C.c_void_p(_ptr(buf)),
                                C.c_void_p(_stream_ptr(stream))), "fks_halo_pack")
 
 
-def halo_unpack(f_ext, buf, nx: int, ny: int, nz: int, n: int, face: int, stream=None):
-    """Unpacks a message that left the neighbouring slab through `face` into the ghost plane it enters."""
-    sp = _slab_args(f_ext, buf, nx, ny, nz, n, face)
-    _check(lib().fks_halo_unpack(C.c_void_p(_ptr(f_ext)), C.byref(sp), n, face, C.c_void_p(_ptr(buf)),
-                                 C.c_void_p(_stream_ptr(stream))), "fks_halo_unpack")
-
-
-def transport_shift_slab(f_ext_in, f_ext_out, nx: int, ny: int, nz: int, dx: float, bc_xy, n: int, T: float,
-                         dt: float, offsets, bc_f=None, stream=None):
-    """Transport step of a z slab with filled ghost planes: owned planes of f_ext_in -> f_ext_out
-    (both [nz + 2, ny, nx, n^3]); offsets as in transport_shift (updated)."""
+def transport_shift_slab(f_in, f_out, nx: int, ny: int, nz: int, dx: float, bc_xy, n: int, T: float,
+                         dt: float, offsets, from_below, from_above, bc_f=None, stream=None):
+    """Transport step of a z slab, f_in -> f_out (both [nz, ny, nx, n^3]); what enters through the
+    z faces comes from the messages the neighbours packed (from_below: the slab below's z+ message,
+    from_above: the slab above's z- message).  offsets as in transport_shift (updated)."""
     import numpy as np
-    total = (nz + 2) * nx * ny * n ** 3
-    _require_device_f64(f_ext_in, "f_ext_in", total)
-    _require_device_f64(f_ext_out, "f_ext_out", total)
+    total = nz * nx * ny * n ** 3
+    _require_device_f64(f_in, "f_in", total)
+    _require_device_f64(f_out, "f_out", total)
+    _require_device_f64(from_below, "from_below", halo_size(nx, ny, nz, n, FACE_ZHI) // 8)
+    _require_device_f64(from_above, "from_above", halo_size(nx, ny, nz, n, FACE_ZLO) // 8)
     if bc_f is not None:
         _require_device_f64(bc_f, "bc_f", 6 * n ** 3)
     if not (isinstance(offsets, np.ndarray) and offsets.dtype == np.float64 and offsets.size == 3 * n
             and offsets.flags.c_contiguous):
         raise ValueError("offsets must be a contiguous float64 numpy array of 3*n values")
     sp = SpaceDesc(nx, ny, nz, dx, (C.c_int32 * 3)(bc_xy[0], bc_xy[1], BC_PERIODIC))
-    _check(lib().fks_transport_shift_slab(C.c_void_p(_ptr(f_ext_in)), C.c_void_p(_ptr(f_ext_out)), C.byref(sp),
-                                          n, T, dt, C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(bc_f)),
+    _check(lib().fks_transport_shift_slab(C.c_void_p(_ptr(f_in)), C.c_void_p(_ptr(f_out)), C.byref(sp),
+                                          n, T, dt, C.c_void_p(offsets.ctypes.data), C.c_void_p(_ptr(from_below)),
+                                          C.c_void_p(_ptr(from_above)), C.c_void_p(_ptr(bc_f)),
                                           C.c_void_p(_stream_ptr(stream))), "fks_transport_shift_slab")
 
 

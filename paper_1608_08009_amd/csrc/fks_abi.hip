@@ -619,10 +619,13 @@ static std::vector<Schedule> schedule_candidates(const fks_segment& s) {
 
 // Transport step shared by the whole-grid and the slab entry points: validation, the
 // per-axis displacement update and integer shifts (host, FP64), then the shift kernel.
-// A slab reads its z neighbours from the ghost planes, so its z shift must be -1, 0 or 1.
+// A slab reads its z neighbours from their messages, so its z shift must be -1, 0 or 1.
 static fks_status transport_step(const double* f_in, double* f_out, const fks_space_desc* sp, int32_t n, double T,
-                                 double dt, double* offsets, const double* bc_f, void* hip_stream, bool slab) {
+                                 double dt, double* offsets, const double* bc_f, void* hip_stream,
+                                 const double* from_below, const double* from_above) {
+    const bool slab = from_below != nullptr || from_above != nullptr;
     if (!f_in || !f_out || !sp || !offsets) return FKS_ERR_INVALID;
+    if (slab && !(from_below && from_above)) return FKS_ERR_INVALID;
     if (n < 2 || n > 64 || !(T > 0) || !std::isfinite(T) || !std::isfinite(dt)) return FKS_ERR_INVALID;
     if (sp->nx < 1 || sp->ny < 1 || sp->nz < 1 || !(sp->dx > 0) || !std::isfinite(sp->dx)) return FKS_ERR_INVALID;
     bool any_dirichlet = false;
@@ -631,8 +634,7 @@ static fks_status transport_step(const double* f_in, double* f_out, const fks_sp
         any_dirichlet |= sp->bc[a] == FKS_BC_DIRICHLET;
     }
     if (any_dirichlet && !bc_f) return FKS_ERR_INVALID;
-    const size_t plane = (size_t)sp->nx * sp->ny * n * n * n * sizeof(double);
-    const size_t bytes = plane * (sp->nz + (slab ? 2 : 0));
+    const size_t bytes = (size_t)sp->nx * sp->ny * sp->nz * n * n * n * sizeof(double);
     const char* a = (const char*)f_in;
     const char* b = (const char*)f_out;
     if (a < b + bytes && b < a + bytes) return FKS_ERR_INVALID;
@@ -648,15 +650,14 @@ static fks_status transport_step(const double* f_in, double* f_out, const fks_sp
             double d0 = std::floor(s0 / sp->dx + 0.5), d1 = std::floor(s1 / sp->dx + 0.5);
             double dd = d1 - d0;
             if (dd > 127 || dd < -127) return FKS_ERR_INVALID;
-            // a slab's ghost planes hold only what crosses its faces: a z shift of +1 is
-            // allowed for the velocities sent up (v_z > 0), -1 for those sent down (v_z < 0)
+            // a slab's messages hold only what crosses its faces: a z shift of +1 is allowed
+            // for the velocities sent up (v_z > 0), -1 for those sent down (v_z < 0)
             if (slab && ax == 2 && dd != 0 && !(dd == 1 && 2 * k > n) && !(dd == -1 && 2 * k < n))
                 return FKS_ERR_INVALID;
             sh.s[ax][k] = (int8_t)dd;
             next[ax][k] = s1;
         }
-    const size_t skip = slab ? plane / sizeof(double) : 0;   // the first owned plane
-    hipError_t e = transport(f_in + skip, f_out + skip, *sp, n, sh, bc_f, (hipStream_t)hip_stream, slab);
+    hipError_t e = transport(f_in, f_out, *sp, n, sh, bc_f, (hipStream_t)hip_stream, from_below, from_above);
     if (e != hipSuccess) return FKS_ERR_DEVICE;
     for (int ax = 0; ax < 3; ++ax)
         for (int k = 0; k < n; ++k) offsets[ax * n + k] = next[ax][k];
@@ -856,13 +857,14 @@ fks_status fks_bgk(const fks_bgk_desc* d, const double* f, double* q_out, double
 
 fks_status fks_transport_shift(const double* f_in, double* f_out, const fks_space_desc* sp, int32_t n,
                                double T, double dt, double* offsets, const double* bc_f, void* hip_stream) {
-    return transport_step(f_in, f_out, sp, n, T, dt, offsets, bc_f, hip_stream, false);
+    return transport_step(f_in, f_out, sp, n, T, dt, offsets, bc_f, hip_stream, nullptr, nullptr);
 }
 
-fks_status fks_transport_shift_slab(const double* f_ext_in, double* f_ext_out, const fks_space_desc* slab,
-                                    int32_t n, double T, double dt, double* offsets, const double* bc_f,
-                                    void* hip_stream) {
-    return transport_step(f_ext_in, f_ext_out, slab, n, T, dt, offsets, bc_f, hip_stream, true);
+fks_status fks_transport_shift_slab(const double* f_in, double* f_out, const fks_space_desc* slab, int32_t n,
+                                    double T, double dt, double* offsets, const double* from_below,
+                                    const double* from_above, const double* bc_f, void* hip_stream) {
+    if (!from_below || !from_above) return FKS_ERR_INVALID;
+    return transport_step(f_in, f_out, slab, n, T, dt, offsets, bc_f, hip_stream, from_below, from_above);
 }
 
 fks_status fks_halo_size(const fks_space_desc* slab, int32_t n, int32_t face, size_t* bytes) {
@@ -873,25 +875,13 @@ fks_status fks_halo_size(const fks_space_desc* slab, int32_t n, int32_t face, si
     return FKS_OK;
 }
 
-fks_status fks_halo_pack(const double* f_ext, const fks_space_desc* slab, int32_t n, int32_t face, double* buf,
+fks_status fks_halo_pack(const double* f, const fks_space_desc* slab, int32_t n, int32_t face, double* buf,
                          void* hip_stream) {
     int k0 = 0, h = 0;
-    if (!f_ext || !buf || !slab_valid(slab, n) || !halo_range(n, face, &k0, &h)) return FKS_ERR_INVALID;
-    // the outgoing velocities of the first (z-) or last (z+) owned plane
-    const int64_t plane = face == FKS_FACE_ZLO ? 1 : slab->nz;
-    hipError_t e = halo_copy(const_cast<double*>(f_ext), buf, plane, (int64_t)slab->nx * slab->ny, n, k0, h, true,
-                             (hipStream_t)hip_stream);
-    return e == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
-}
-
-fks_status fks_halo_unpack(double* f_ext, const fks_space_desc* slab, int32_t n, int32_t face, const double* buf,
-                           void* hip_stream) {
-    int k0 = 0, h = 0;
-    // a message that left a neighbour through `face` enters this slab through the opposite face
-    if (!f_ext || !buf || !slab_valid(slab, n) || !halo_range(n, face, &k0, &h)) return FKS_ERR_INVALID;
-    const int64_t ghost = face == FKS_FACE_ZHI ? 0 : slab->nz + 1;
-    hipError_t e = halo_copy(f_ext, const_cast<double*>(buf), ghost, (int64_t)slab->nx * slab->ny, n, k0, h, false,
-                             (hipStream_t)hip_stream);
+    if (!f || !buf || !slab_valid(slab, n) || !halo_range(n, face, &k0, &h)) return FKS_ERR_INVALID;
+    // the outgoing velocities of the first (z-) or last (z+) plane
+    const int64_t plane = face == FKS_FACE_ZLO ? 0 : slab->nz - 1;
+    hipError_t e = halo_pack(f, buf, plane, (int64_t)slab->nx * slab->ny, n, k0, h, (hipStream_t)hip_stream);
     return e == hipSuccess ? FKS_OK : FKS_ERR_DEVICE;
 }
 

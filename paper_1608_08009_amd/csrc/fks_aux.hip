@@ -13,7 +13,6 @@ namespace fks {
 namespace {
 
 constexpr int kBS = 256;
-constexpr int kBcSlab = 2;   // z axis of a slab with ghost planes (not a public boundary condition)
 typedef double d2v __attribute__((ext_vector_type(2)));
 
 // U[c] = dv^3 sum_j f_j (1, vx, vy, vz, |v|^2)
@@ -77,9 +76,8 @@ __global__ __launch_bounds__(kBS) void k_conserve(double* __restrict__ f, const 
     }
 }
 
-// source index along one axis of a destination index i shifted by sh: periodic wrap, or -1
-// when a Dirichlet axis reaches outside (the inflow face), or the unwrapped index for the z
-// axis of a slab (its ghost planes sit at -1 and nz)
+// source index along one axis of a destination index i shifted by sh: periodic wrap, or
+// `outside` when a Dirichlet axis reaches beyond the grid (the inflow face)
 __device__ __forceinline__ int source_index(int i, int sh, int dim, int bc, bool& outside) {
     int s = i - sh;
     if (bc == FKS_BC_PERIODIC) {
@@ -89,7 +87,7 @@ __device__ __forceinline__ int source_index(int i, int sh, int dim, int bc, bool
             s %= dim;
             if (s < 0) s += dim;
         }
-    } else if (bc != kBcSlab && (s < 0 || s >= dim)) {
+    } else if (s < 0 || s >= dim) {
         outside = true;
     }
     return s;
@@ -109,21 +107,29 @@ __device__ __forceinline__ void divmod_small(int k, int n, float inv_n, int& q, 
     }
 }
 
-// out[iz][iy][ix][k] = in[iz - sz][iy - sy][ix - sx][k]   (periodic or Dirichlet inflow)
+// Messages entering a z slab (layout [iy][ix][kx][ky][h], see k_halo): from below, the
+// velocities with v_z > 0 (kz in [up0, up0 + hup)); from above, those with v_z < 0 (kz < hdn)
+struct SlabIn {
+    const double* below;
+    const double* above;
+    int up0, hup, hdn;
+};
+
+// out[iz][iy][ix][k] = in[iz - sz][iy - sy][ix - sx][k]   (periodic or Dirichlet inflow; in
+// slab mode, source planes -1 and nz are the messages from the neighbours below and above)
 // One (x, y) column of cells per grid row (blockIdx.y, strided), walked along z, so the cell
 // coordinates are uniform.  The z shift splits a velocity row (fixed kx, ky) of a source cell
 // into up to three runs that land in three consecutive output cells of one column: walking
 // the column keeps those reads on one CU, where the second and third runs hit the lines the
-// first one brought into the cache.  A workgroup reads 4 KB per cell (U = 1), small enough
-// that those lines are still there: cells in grid order fetched 2.3 to 3 times the
-// algorithmic bytes, the column walk with 16 KB per cell (U = 4) 2.1 times, with 4 KB 1.35
-// to 1.6 times.  Lanes run over a cell's velocities in groups of V consecutive kz (V = 2 for
-// even n: 16-byte accesses where the two kz share their z shift, as they do everywhere
-// except around v_z = 0).
-template <int V, int U>
+// first one brought into the cache.  A workgroup reads 4 KB per cell, small enough that those
+// lines are still there: cells in grid order fetched 2.3 to 3 times the algorithmic bytes,
+// the column walk with 16 KB per cell 2.1 times, with 4 KB 1.35 to 1.6 times.  Lanes run over
+// a cell's velocities in groups of V consecutive kz (V = 2 for even n: 16-byte accesses where
+// the two kz share their source, as they do everywhere except around v_z = 0).
+template <int V, bool SLAB>
 __global__ __launch_bounds__(kBS) void k_transport(const double* __restrict__ in, double* __restrict__ out,
                                                    int nx, int ny, int nz, int bcx, int bcy, int bcz, int n,
-                                                   ShiftTable sh, const double* __restrict__ bc_f) {
+                                                   ShiftTable sh, const double* __restrict__ bc_f, SlabIn msg) {
     __shared__ int8_t sl[3][64];
     if (threadIdx.x < 3 * 64) sl[threadIdx.x / 64][threadIdx.x % 64] = sh.s[threadIdx.x / 64][threadIdx.x % 64];
     __syncthreads();
@@ -131,86 +137,81 @@ __global__ __launch_bounds__(kBS) void k_transport(const double* __restrict__ in
     const int ngroup = nv / V;
     const int64_t ncol = (int64_t)nx * ny;
     const float inv_n = 1.0f / (float)n;
-    for (int64_t col = blockIdx.y; col < ncol; col += gridDim.y)
-    for (int iz = 0; iz < nz; ++iz) {
+    const int g = blockIdx.x * kBS + threadIdx.x;
+    if (g >= ngroup) return;   // no barrier below
+    const int k = g * V;
+    int kxy, kz, kx, ky;
+    divmod_small(k, n, inv_n, kxy, kz);
+    divmod_small(kxy, n, inv_n, kx, ky);
+    for (int64_t col = blockIdx.y; col < ncol; col += gridDim.y) {
         const int ix = (int)(col % nx), iy = (int)(col / nx);
-        const int64_t cell = iz * ncol + col;
-        double v[U][V];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int g = (blockIdx.x * U + u) * kBS + threadIdx.x;
-            if (g >= ngroup) break;
-            const int k = g * V;
-            int kxy, kz, kx, ky;
-            divmod_small(k, n, inv_n, kxy, kz);
-            divmod_small(kxy, n, inv_n, kx, ky);
-            bool outx = false, outy = false;
-            const int sx = source_index(ix, sl[0][kx], nx, bcx, outx);
-            const int sy = source_index(iy, sl[1][ky], ny, bcy, outy);
+        bool outx = false, outy = false;
+        const int sx = source_index(ix, sl[0][kx], nx, bcx, outx);
+        const int sy = source_index(iy, sl[1][ky], ny, bcy, outy);
+        const int64_t src_col = (int64_t)sy * nx + sx;
+        for (int iz = 0; iz < nz; ++iz) {
+            double v[V];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 bool outz = false;
-                const int sz = source_index(iz, sl[2][kz + e], nz, bcz, outz);
+                int sz;
+                if (SLAB) sz = iz - sl[2][kz + e];   // -1 or nz: a neighbour's message
+                else sz = source_index(iz, sl[2][kz + e], nz, bcz, outz);
                 // the first out-of-range axis in x, y, z order decides the inflow face
                 const int face = outx ? (sx < 0 ? 0 : 1) : outy ? (sy < 0 ? 2 : 3) : outz ? (sz < 0 ? 4 : 5) : -1;
-                if (V == 2 && e == 0 && face < 0 && sl[2][kz] == sl[2][kz + 1]) {
+                const bool inside = face < 0 && (!SLAB || (sz >= 0 && sz < nz));
+                if (V == 2 && e == 0 && inside && sl[2][kz] == sl[2][kz + 1]) {
                     // both kz from the same source cell: one 16-byte load
-                    const double2 w = *reinterpret_cast<const double2*>(
-                        in + (((int64_t)sz * ny + sy) * nx + sx) * nv + k);
-                    v[u][0] = w.x;
-                    v[u][V - 1] = w.y;
+                    const double2 w = *reinterpret_cast<const double2*>(in + (sz * ncol + src_col) * nv + k);
+                    v[0] = w.x;
+                    v[V - 1] = w.y;
                     break;
                 }
-                v[u][e] = face >= 0 ? bc_f[(int64_t)face * nv + k + e]
-                                    : in[(((int64_t)sz * ny + sy) * nx + sx) * nv + k + e];
+                if (face >= 0) {
+                    v[e] = bc_f[(int64_t)face * nv + k + e];
+                } else if (inside) {
+                    v[e] = in[(sz * ncol + src_col) * nv + k + e];
+                } else {
+                    const int64_t row = (src_col * n + kx) * n + ky;
+                    v[e] = sz < 0 ? msg.below[row * msg.hup + (kz + e - msg.up0)] : msg.above[row * msg.hdn + kz + e];
+                }
             }
-        }
-        double* const o = out + cell * nv;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int g = (blockIdx.x * U + u) * kBS + threadIdx.x;
-            if (g >= ngroup) break;
+            double* const o = out + (iz * ncol + col) * nv + k;
             if (V == 2) {
-                __builtin_nontemporal_store(d2v{v[u][0], v[u][V - 1]}, reinterpret_cast<d2v*>(o + g * V));
+                __builtin_nontemporal_store(d2v{v[0], v[V - 1]}, reinterpret_cast<d2v*>(o));
             } else {
-                __builtin_nontemporal_store(v[u][0], o + g);
+                __builtin_nontemporal_store(v[0], o);
             }
         }
     }
 }
 
-// Halo messages of a z slab: the n x n x h velocities of every cell of one plane whose
-// kz lies in [k0, k0 + h), as buf[iy][ix][kx][ky][h].  pack copies them out of plane
-// `plane` of f, unpack copies them into it; consecutive threads take consecutive buffer
-// entries (coalesced writes for pack, coalesced reads for unpack; the f side is read or
-// written in runs of h doubles).
-template <bool PACK>
-__global__ __launch_bounds__(kBS) void k_halo(double* __restrict__ f, double* __restrict__ buf, int64_t plane,
-                                              int64_t ncell_plane, int n, int k0, int h) {
+// Halo message of a z slab: the n x n x h velocities of every cell of one plane whose kz
+// lies in [k0, k0 + h), as buf[iy][ix][kx][ky][h]; consecutive threads write consecutive
+// buffer entries (the plane is read in runs of h doubles).
+__global__ __launch_bounds__(kBS) void k_halo_pack(const double* __restrict__ f, double* __restrict__ buf,
+                                                   int64_t plane, int64_t ncell_plane, int n, int k0, int h) {
     const int64_t nv = (int64_t)n * n * n;
     const int64_t rows = ncell_plane * n * n;   // (cell, kx, ky) rows of the plane
     const int64_t total = rows * h;
-    double* const base = f + plane * ncell_plane * nv;
+    const double* const base = f + plane * ncell_plane * nv;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = t / h;
         const int j = (int)(t - row * h);
-        double* const g = base + row * n + k0 + j;   // row r = (cell, kx, ky): n^2 rows per cell
-        if (PACK) buf[t] = *g;
-        else *g = buf[t];
+        buf[t] = base[row * n + k0 + j];   // row r = (cell, kx, ky): n^2 rows per cell
     }
 }
 
 }  // namespace
 
-hipError_t halo_copy(double* f, double* buf, int64_t plane, int64_t ncell_plane, int n, int k0, int h, bool pack,
+hipError_t halo_pack(const double* f, double* buf, int64_t plane, int64_t ncell_plane, int n, int k0, int h,
                      hipStream_t st) {
     const int64_t total = ncell_plane * n * n * h;
     if (total == 0) return hipSuccess;
     int64_t blocks = (total + kBS - 1) / kBS;
     if (blocks > 65536) blocks = 65536;
-    if (pack) k_halo<true><<<(unsigned)blocks, kBS, 0, st>>>(f, buf, plane, ncell_plane, n, k0, h);
-    else k_halo<false><<<(unsigned)blocks, kBS, 0, st>>>(f, buf, plane, ncell_plane, n, k0, h);
+    k_halo_pack<<<(unsigned)blocks, kBS, 0, st>>>(f, buf, plane, ncell_plane, n, k0, h);
     return hipGetLastError();
 }
 
@@ -227,23 +228,26 @@ hipError_t conserve(double* f, const double* U, int64_t ncell, int n, double T, 
 }
 
 hipError_t transport(const double* f_in, double* f_out, const fks_space_desc& sp, int n, const ShiftTable& sh,
-                     const double* bc_f, hipStream_t st, bool slab) {
+                     const double* bc_f, hipStream_t st, const double* from_below, const double* from_above) {
     // 16-byte accesses need even n and 16-byte aligned arrays (any double pointer is accepted)
     const bool aligned = ((uintptr_t)f_in | (uintptr_t)f_out | (uintptr_t)bc_f) % 16 == 0;
     const int V = (n % 2 == 0 && aligned) ? 2 : 1;
-    constexpr int U = 1;
     const int ngroup = n * n * n / V;
-    const int gx = (ngroup + kBS * U - 1) / (kBS * U);
+    const int gx = (ngroup + kBS - 1) / kBS;
     // one grid row per (x, y) column, up to about 32k workgroups in all
     const int64_t ncol = (int64_t)sp.nx * sp.ny;
     const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>({ncol, 65535, 32768 / gx}));
-    const int bcz = slab ? kBcSlab : sp.bc[2];
-    if (V == 2)
-        k_transport<2, U><<<dim3((unsigned)gx, gy), kBS, 0, st>>>(f_in, f_out, sp.nx, sp.ny, sp.nz, sp.bc[0], sp.bc[1], bcz, n, sh,
-                                                     bc_f);
-    else
-        k_transport<1, U><<<dim3((unsigned)gx, gy), kBS, 0, st>>>(f_in, f_out, sp.nx, sp.ny, sp.nz, sp.bc[0], sp.bc[1], bcz, n, sh,
-                                                     bc_f);
+    const bool slab = from_below != nullptr;
+    const SlabIn msg{from_below, from_above, n / 2 + 1, n - 1 - n / 2, (n + 1) / 2};
+    const dim3 grid((unsigned)gx, gy);
+#define FKS_TRANSPORT(VV, SS)                                                                                 \
+    k_transport<VV, SS><<<grid, kBS, 0, st>>>(f_in, f_out, sp.nx, sp.ny, sp.nz, sp.bc[0], sp.bc[1], sp.bc[2], n, \
+                                              sh, bc_f, msg)
+    if (V == 2 && slab) FKS_TRANSPORT(2, true);
+    else if (V == 2) FKS_TRANSPORT(2, false);
+    else if (slab) FKS_TRANSPORT(1, true);
+    else FKS_TRANSPORT(1, false);
+#undef FKS_TRANSPORT
     return hipGetLastError();
 }
 

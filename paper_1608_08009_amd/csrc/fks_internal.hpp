@@ -120,13 +120,15 @@ hipError_t bgk(const fks_bgk_desc& d, const double* f, double* q_out, double* f_
 GridConst grid_const(int n, double T);
 hipError_t moments(const double* f, int64_t ncell, int n, double T, double* U, hipStream_t stream);
 hipError_t conserve(double* f, const double* U, int64_t ncell, int n, double T, hipStream_t stream);
-// slab: sp.nz owned planes between two ghost planes; f_in and f_out point at the first
-// owned plane, and the z shift (|s| <= 1) reads the ghosts instead of a boundary condition
+// from_below == nullptr: the whole grid, z by sp.bc[2].  Otherwise one z slab: source planes
+// -1 and nz are the messages from the neighbours below (v_z > 0) and above (v_z < 0), laid
+// out as halo_pack writes them; the host has checked that the z shift stays within them
 hipError_t transport(const double* f_in, double* f_out, const fks_space_desc& sp, int n,
-                     const ShiftTable& shift, const double* bc_f, hipStream_t stream, bool slab);
-// copies the kz range [k0, k0 + h) of every velocity row of one plane of f out to buf
-// (pack) or from buf into it (unpack); buf is [ncell_plane][n][n][h]
-hipError_t halo_copy(double* f, double* buf, int64_t plane, int64_t ncell_plane, int n, int k0, int h, bool pack,
+                     const ShiftTable& shift, const double* bc_f, hipStream_t stream, const double* from_below,
+                     const double* from_above);
+// copies the kz range [k0, k0 + h) of every velocity row of one plane of f to buf
+// [ncell_plane][n][n][h]
+hipError_t halo_pack(const double* f, double* buf, int64_t plane, int64_t ncell_plane, int n, int k0, int h,
                      hipStream_t stream);
 
 }  // namespace fks

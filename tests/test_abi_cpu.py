@@ -199,12 +199,18 @@ def test_halo_sizes_and_rejections_on_the_host():
     fake_a, fake_b = C.c_void_p(1 << 20), C.c_void_p(1 << 40)   # never dereferenced: rejected first
     assert L.fks_halo_pack(None, C.byref(sp), 4, 0, fake_b, None) == fks.FKS_ERR_INVALID
     assert L.fks_halo_pack(fake_a, C.byref(sp), 4, 3, fake_b, None) == fks.FKS_ERR_INVALID
-    assert L.fks_halo_unpack(fake_a, C.byref(sp), 4, 1, None, None) == fks.FKS_ERR_INVALID
-    assert L.fks_halo_unpack(fake_a, None, 4, 1, fake_b, None) == fks.FKS_ERR_INVALID
-    # a slab step whose z shift exceeds what the ghost planes hold is refused, offsets untouched
+    assert L.fks_halo_pack(fake_a, None, 4, 1, fake_b, None) == fks.FKS_ERR_INVALID
+    assert L.fks_halo_pack(fake_a, C.byref(sp), 4, 1, None, None) == fks.FKS_ERR_INVALID
+    # a slab step whose z shift exceeds what the messages hold is refused, offsets untouched;
+    # so is a step without both messages
     n, T = 4, 2.0
     off = np.zeros((3, n))
+    msg_a, msg_b = C.c_void_p(1 << 42), C.c_void_p(1 << 43)
     for dt in (2.2 * 0.25 / T, -0.5 * 0.25 / T):
         assert L.fks_transport_shift_slab(fake_a, fake_b, C.byref(sp), n, T, dt, C.c_void_p(off.ctypes.data),
-                                          None, None) == fks.FKS_ERR_INVALID
+                                          msg_a, msg_b, None, None) == fks.FKS_ERR_INVALID
+        assert not off.any()
+    for below, above in ((None, msg_b), (msg_a, None)):
+        assert L.fks_transport_shift_slab(fake_a, fake_b, C.byref(sp), n, T, 0.1, C.c_void_p(off.ctypes.data),
+                                          below, above, None, None) == fks.FKS_ERR_INVALID
         assert not off.any()
