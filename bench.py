@@ -308,6 +308,43 @@ def main():
                                  "frac": round(alg / (ms_bgk * 1e-3) / 8e12, 4), "bytes_per_launch": alg}}
         print(f"[bench] bgk: {ms_bgk:.3f} ms per batch", file=sys.stderr, flush=True)
 
+    # moments and the projection onto prescribed moments on the same batch (FP64, in place)
+    moments_line = None
+    if args.extras:
+        Um = torch.empty((NCELL, 5), dtype=torch.float64, device="cuda")
+        fks.moments(fa, N_V, T_BOX, U=Um)
+        fks.conserve(fa, Um, N_V, T_BOX)
+        torch.cuda.synchronize()
+        reps = 10
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(reps):                  # back to back: the launches stay ahead of the GPU
+            fks.moments(fa, N_V, T_BOX, U=Um)
+        ev[1].record(stream)
+        for _ in range(reps):
+            fks.conserve(fa, Um, N_V, T_BOX)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        ms_m = ev[0].elapsed_time(ev[1]) / reps
+        ms_c = ev[1].elapsed_time(ev[2]) / reps
+        pts = NCELL * N_V ** 3
+        moments_line = {"workload": f"{NCELL} cells of 32^3, FP64: fks_moments, then fks_conserve onto those moments "
+                                    "(in place)",
+                        "ms_moments": round(ms_m, 4), "ms_conserve": round(ms_c, 4),
+                        "value": pts / (ms_m * 1e-3), "unit": UNIT,
+                        "roofline": {"bound": "hbm", "achieved": round(8.0 * pts / (ms_m * 1e-3) / 1e9, 1),
+                                     "peak": 8000.0, "unit": "GB/s",
+                                     "frac": round(8.0 * pts / (ms_m * 1e-3) / 8e12, 4),
+                                     "bytes_per_launch": 8.0 * pts, "kernel": "k_moments (read f once)"},
+                        "conserve_roofline": {"bound": "hbm",
+                                              "achieved": round(24.0 * pts / (ms_c * 1e-3) / 1e9, 1),
+                                              "peak": 8000.0, "unit": "GB/s",
+                                              "frac": round(24.0 * pts / (ms_c * 1e-3) / 8e12, 4),
+                                              "bytes_per_launch": 24.0 * pts,
+                                              "bytes": "f read for the sums, read and written for the correction"}}
+        del Um
+        print(f"[bench] moments: {ms_m:.3f} ms, conserve {ms_c:.3f} ms", file=sys.stderr, flush=True)
+
     # z-slab transport with halo exchange: one GPU's share of the 32^3-cell, 24^3-velocity flow on
     # eight GPUs (4 planes of 32 x 32 cells).  Per step: pack the two outgoing messages, then the
     # slab transport, which reads what enters through the z faces from the incoming messages
@@ -574,6 +611,7 @@ def main():
         "collide2d": d2_line,
         "dealias": dealias_line,
         "halo": halo_line,
+        "moments": moments_line,
         "uneven": uneven_line,
     }
     print(json.dumps(line), flush=True)

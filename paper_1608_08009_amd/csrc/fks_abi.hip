@@ -195,15 +195,30 @@ GridConst grid_const(int n, double T) {
     GridConst g{};
     g.T = T;
     g.dv = 2.0 * T / n;
+    // Gram matrix of the scaled basis (1, u, |u|^2), u = v/T, over the n^3 nodes.  The grid is
+    // a tensor product, so every entry is a product of the 1D power sums S_k = sum_i u_i^k
+    // (O(n) work: the n^3 triple loop cost about a millisecond of host time per call)
+    long double S[5] = {};
+    for (int i = 0; i < n; ++i) {
+        const long double u = (-T + i * g.dv) / T;
+        long double pw = 1.0L;
+        for (int k = 0; k < 5; ++k) {
+            S[k] += pw;
+            pw *= u;
+        }
+    }
+    const long double N = S[0];
     long double G[5][5] = {};
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j)
-            for (int k = 0; k < n; ++k) {
-                long double vx = (-T + i * g.dv) / T, vy = (-T + j * g.dv) / T, vz = (-T + k * g.dv) / T;
-                long double ph[5] = {1.0L, vx, vy, vz, vx * vx + vy * vy + vz * vz};
-                for (int a = 0; a < 5; ++a)
-                    for (int b = 0; b < 5; ++b) G[a][b] += ph[a] * ph[b];
-            }
+    G[0][0] = N * N * N;
+    G[0][4] = G[4][0] = 3.0L * S[2] * N * N;                        // sum |u|^2
+    G[4][4] = 3.0L * S[4] * N * N + 6.0L * S[2] * S[2] * N;         // sum |u|^4
+    for (int a = 1; a <= 3; ++a) {
+        G[0][a] = G[a][0] = S[1] * N * N;                           // sum u_a
+        G[a][a] = S[2] * N * N;                                     // sum u_a^2
+        G[a][4] = G[4][a] = S[3] * N * N + 2.0L * S[1] * S[2] * N;  // sum u_a |u|^2
+        for (int b = 1; b <= 3; ++b)
+            if (b != a) G[a][b] = S[1] * S[1] * N;                  // sum u_a u_b
+    }
     long double A[5][10] = {};
     for (int a = 0; a < 5; ++a) {
         for (int b = 0; b < 5; ++b) A[a][b] = G[a][b];

@@ -15,6 +15,36 @@ namespace {
 constexpr int kBS = 256;
 typedef double d2v __attribute__((ext_vector_type(2)));
 
+// Grid indices of i, i + kBS, i + 2 kBS, ... without a division per element: the first
+// (x, y, z) by division, then steps of kBS = (dx, dy, dz) in mixed radix n with carries
+// (dz, dy < n, so each carry is at most one).
+struct Walk {
+    int x, y, z, dx, dy, dz, n;
+    __device__ Walk(int i, int n_) : n(n_) {
+        z = i % n;
+        y = (i / n) % n;
+        x = i / (n * n);
+        dz = kBS % n;
+        dy = (kBS / n) % n;
+        dx = kBS / (n * n);
+    }
+    __device__ __forceinline__ void step() {
+        z += dz;
+        int cy = 0;
+        if (z >= n) {
+            z -= n;
+            cy = 1;
+        }
+        y += dy + cy;
+        int cx = 0;
+        if (y >= n) {
+            y -= n;
+            cx = 1;
+        }
+        x += dx + cx;
+    }
+};
+
 // U[c] = dv^3 sum_j f_j (1, vx, vy, vz, |v|^2)
 __global__ __launch_bounds__(kBS) void k_moments(const double* __restrict__ f, int n, GridConst gc,
                                                  double* __restrict__ U) {
@@ -23,21 +53,29 @@ __global__ __launch_bounds__(kBS) void k_moments(const double* __restrict__ f, i
     const int nn = n * n * n;
     const double* fc = f + c * nn;
     double m[5] = {0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < nn; i += kBS) {
-        const int z = i % n, y = (i / n) % n, x = i / (n * n);
-        const double vx = -gc.T + x * gc.dv, vy = -gc.T + y * gc.dv, vz = -gc.T + z * gc.dv;
+    Walk w(threadIdx.x, n);
+#pragma unroll 8   // eight loads in flight per thread: one at a time left the kernel latency-bound
+    for (int i = threadIdx.x; i < nn; i += kBS, w.step()) {
+        const double vx = fma((double)w.x, gc.dv, -gc.T), vy = fma((double)w.y, gc.dv, -gc.T),
+                     vz = fma((double)w.z, gc.dv, -gc.T);
         const double v = fc[i];
         m[0] += v;
         m[1] = fma(v, vx, m[1]);
         m[2] = fma(v, vy, m[2]);
         m[3] = fma(v, vz, m[3]);
-        m[4] = fma(v, vx * vx + vy * vy + vz * vz, m[4]);
+        m[4] = fma(v, fma(vx, vx, fma(vy, vy, vz * vz)), m[4]);
     }
     block_sum5<kBS>(m, red);
     if (threadIdx.x == 0) {
         const double dv3 = gc.dv * gc.dv * gc.dv;
         for (int a = 0; a < 5; ++a) U[c * 5 + a] = dv3 * m[a];
     }
+}
+
+// the scaled basis (1, v/T, |v|^2/T^2) at grid point (x, y, z); h = dv / T
+__device__ __forceinline__ Basis scaled_basis(const Walk& w, double h) {
+    const double ux = fma((double)w.x, h, -1.0), uy = fma((double)w.y, h, -1.0), uz = fma((double)w.z, h, -1.0);
+    return Basis{{1.0, ux, uy, uz, fma(ux, ux, fma(uy, uy, uz * uz))}};
 }
 
 // f <- f + C^T (C C^T)^{-1} (U - C f), in the scaled basis
@@ -47,14 +85,18 @@ __global__ __launch_bounds__(kBS) void k_conserve(double* __restrict__ f, const 
     __shared__ double lam_s[5];
     const int64_t c = blockIdx.x;
     const int nn = n * n * n;
+    const double h = gc.dv / gc.T;
     double* fc = f + c * nn;
     double m[5] = {0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < nn; i += kBS) {
-        const int z = i % n, y = (i / n) % n, x = i / (n * n);
-        const Basis b = basis_at(gc, x, y, z);
-        const double v = fc[i];
+    {
+        Walk w(threadIdx.x, n);
+#pragma unroll 8
+        for (int i = threadIdx.x; i < nn; i += kBS, w.step()) {
+            const Basis b = scaled_basis(w, h);
+            const double v = fc[i];
 #pragma unroll
-        for (int a = 0; a < 5; ++a) m[a] = fma(v, b.p[a], m[a]);
+            for (int a = 0; a < 5; ++a) m[a] = fma(v, b.p[a], m[a]);
+        }
     }
     block_sum5<kBS>(m, red);
     if (threadIdx.x == 0) {
@@ -70,10 +112,9 @@ __global__ __launch_bounds__(kBS) void k_conserve(double* __restrict__ f, const 
     double lam[5];
 #pragma unroll
     for (int a = 0; a < 5; ++a) lam[a] = lam_s[a];
-    for (int i = threadIdx.x; i < nn; i += kBS) {
-        const int z = i % n, y = (i / n) % n, x = i / (n * n);
-        fc[i] += correction(lam, basis_at(gc, x, y, z));
-    }
+    Walk w(threadIdx.x, n);
+#pragma unroll 8
+    for (int i = threadIdx.x; i < nn; i += kBS, w.step()) fc[i] += correction(lam, scaled_basis(w, h));
 }
 
 // source index along one axis of a destination index i shifted by sh: periodic wrap, or
