@@ -76,6 +76,11 @@ def _oracle_extra_worker(args):
         step = lambda g: g + DT_OVER_TAU * O.conserve_Q(O.fks_oracle_dealias.collide_dealias_fast64(g, op),  # noqa: E731
                                                         N_V, T_BOX)
         pts = N_V ** 3
+    elif kind == "moments":
+        # U = C f, then the projection of f onto U, per cell of the batch
+        f = synth.two_maxwellian_cells(N_V, T_BOX, NCELL, first=0, count=1024)
+        step = lambda g: O.project(g, O.moments(g, N_V, T_BOX), N_V, T_BOX)  # noqa: E731
+        pts = N_V ** 3
     elif kind == "halo":
         # the whole-grid transport of the oracle (what the slabs reproduce) on a 2 x 2 x 4 grid of
         # 24^3 velocities, periodic, the bench's CFL; one step is one sample
@@ -105,7 +110,9 @@ def cpu_extras(kinds):
     for kind, count, pts, t in res:
         unit = "cells·N²/s" if kind == "collide2d" else UNIT
         what = (f"{count} whole-grid transport steps of a 2x2x4 grid of 24^3 velocities (the oracle's "
-                "element loop)" if kind == "halo" else f"{count} cells of the same workload")
+                "element loop)" if kind == "halo" else
+                f"{count} cells of the same workload (moments, then projection)" if kind == "moments" else
+                f"{count} cells of the same workload")
         out[kind] = {"value": count * pts / t, "unit": unit, "cores": 1, "kind": "oracle",
                      "sample": f"{what}, numpy FP64, one single-threaded process ({t:.1f} s)"}
     return out
@@ -566,7 +573,7 @@ def main():
 
     # the oracle beside the extra lines (bounded samples, one core each)
     if args.extras and args.cpu_sample > 0:
-        extra_cpu = cpu_extras(["collide2d", "bgk", "dealias", "halo"])
+        extra_cpu = cpu_extras(["collide2d", "bgk", "dealias", "halo", "moments"])
         if d2_line is not None:
             d2_line["cpu_baseline"] = extra_cpu["collide2d"]
         if bgk_line is not None:
@@ -575,6 +582,8 @@ def main():
             dealias_line["cpu_baseline"] = extra_cpu["dealias"]
         if halo_line is not None:
             halo_line["cpu_baseline"] = extra_cpu["halo"]
+        if moments_line is not None:
+            moments_line["cpu_baseline"] = extra_cpu["moments"]
 
     line = {
         "metric": METRIC,
