@@ -163,8 +163,9 @@ struct SlabIn {
 // into up to three runs that land in three consecutive output cells of one column: walking
 // the column keeps those reads on one CU, where the second and third runs hit the lines the
 // first one brought into the cache.  A workgroup reads 4 KB per cell, small enough that those
-// lines are still there: cells in grid order fetched 2.3 to 3 times the algorithmic bytes,
-// the column walk with 16 KB per cell 2.1 times, with 4 KB 1.35 to 1.6 times.  Lanes run over
+// lines are still there: on 32 x 32 x 32 cells of 24^3 velocities, cells in grid order fetched
+// 2.3 to 3 times the algorithmic bytes, the column walk with 16 KB per cell 2.1 times, with
+// 4 KB 1.07 to 1.21 times (1.24 to 1.28 on a 4-plane slab).  Lanes run over
 // a cell's velocities in groups of V consecutive kz (V = 2 for even n: 16-byte accesses where
 // the two kz share their source, as they do everywhere except around v_z = 0).
 template <int V, bool SLAB>
