@@ -414,6 +414,33 @@ def main():
         del sa, sb, msgs
         print(f"[bench] halo: {ms_x:.3f} ms pack, {ms_t:.3f} ms slab transport", file=sys.stderr,
               flush=True)
+        # the whole grid on one GPU: 32 x 32 x 32 cells of 24^3 velocities, periodic
+        wa = torch.rand((8 * hz, hy, hx, hn ** 3), dtype=torch.float64, device="cuda", generator=g)
+        wb = torch.empty_like(wa)
+        offw = np.zeros((3, hn))
+        per3 = (fks.BC_PERIODIC,) * 3
+        for _ in range(2):
+            fks.transport_shift(wa, wb, hx, hy, 8 * hz, hdx, per3, hn, hT, hdt, offw)
+            wa, wb = wb, wa
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 5
+        ev[0].record(stream)
+        for _ in range(reps):
+            fks.transport_shift(wa, wb, hx, hy, 8 * hz, hdx, per3, hn, hT, hdt, offw)
+            wa, wb = wb, wa
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms_w = ev[0].elapsed_time(ev[1]) / reps
+        w_bytes = 8 * hz * hy * hx * hn ** 3 * 16.0
+        halo_line["whole_grid_transport"] = {
+            "workload": f"{hx}x{hy}x{8 * hz} cells of {hn}^3 velocities on one GPU, periodic, CFL 0.95",
+            "ms": round(ms_w, 4), "value": 8 * hz * hy * hx * hn ** 3 / (ms_w * 1e-3), "unit": UNIT,
+            "roofline": {"bound": "hbm", "achieved": round(w_bytes / (ms_w * 1e-3) / 1e9, 1), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(w_bytes / (ms_w * 1e-3) / 8e12, 4),
+                         "bytes_per_launch": w_bytes}}
+        del wa, wb
+        print(f"[bench] whole-grid transport: {ms_w:.3f} ms", file=sys.stderr, flush=True)
 
     # two velocity dimensions: Maxwell molecules, 8192 cells of 32^2, A = 8 (Test 1.1 resolution)
     d2_line = None
