@@ -239,22 +239,29 @@ __global__ __launch_bounds__(128) void g_inv_x(const cx<T>* __restrict__ work0, 
     });
     fft<T, N, 1>(v);
     T* q = hide(acc + (size_t)c * N * N * N + y * N + z);
-    // accumulator read-modify-write in groups of x, fenced so that the compiler does not
-    // load every accumulator at once (which costs the FP64 kernel half its occupancy)
-    constexpr int G = (N % 8 == 0) ? 8 : N;
-    sfor<N / G>([&](auto gI) {
-        constexpr int g0 = decltype(gI)::value * G;
-        T prod[G];
-        sfor<G>([&](auto I) {
-            constexpr int x = g0 + decltype(I)::value;
-            prod[decltype(I)::value] = first ? v[x].x * v[x].y : q[x * N * N] + v[x].x * v[x].y;
+    if (first) {
+        sfor<N>([&](auto I) {
+            constexpr int x = decltype(I)::value;
+            q[x * N * N] = v[x].x * v[x].y;
         });
-        sfor<G>([&](auto I) {
-            constexpr int x = g0 + decltype(I)::value;
-            q[x * N * N] = prod[decltype(I)::value];
+    } else {
+        // Accumulator read-modify-write.  The first-term test stays outside: a load under a
+        // per-element condition is not speculated, and each one then waited for the memory
+        // before the next was issued (48 round trips per thread at n = 48).  FP32 issues
+        // every load before the first store; FP64 goes in fenced groups of x, since loading
+        // every accumulator at once costs that kernel half its occupancy.
+        constexpr int G = (sizeof(T) == 4 || N % 8 != 0) ? N : 8;
+        sfor<N / G>([&](auto gI) {
+            constexpr int g0 = decltype(gI)::value * G;
+            T prod[G];
+            sfor<G>([&](auto I) { prod[decltype(I)::value] = q[(g0 + decltype(I)::value) * N * N]; });
+            sfor<G>([&](auto I) {
+                constexpr int x = g0 + decltype(I)::value;
+                q[x * N * N] = prod[decltype(I)::value] + v[x].x * v[x].y;
+            });
+            __builtin_amdgcn_sched_barrier(0);
         });
-        __builtin_amdgcn_sched_barrier(0);
-    });
+    }
     }
 }
 
@@ -374,21 +381,26 @@ __global__ __launch_bounds__(128) void d_pad_x(const cx<T>* __restrict__ w2, T* 
     });
     fft<T, NP, 1>(v);
     T* q = acc + (size_t)c * NP * NP * NP + yp * NP + zp;
-    // accumulator read-modify-write in fenced groups of x (as in g_inv_x)
-    constexpr int G = (NP % 8 == 0) ? 8 : (NP % 6 == 0 ? 6 : NP);
-    sfor<NP / G>([&](auto gI) {
-        constexpr int g0 = decltype(gI)::value * G;
-        T prod[G];
-        sfor<G>([&](auto I) {
-            constexpr int x = g0 + decltype(I)::value;
-            prod[decltype(I)::value] = first ? v[x].x * v[x].y : q[x * NP * NP] + v[x].x * v[x].y;
+    if (first) {
+        sfor<NP>([&](auto I) {
+            constexpr int x = decltype(I)::value;
+            q[x * NP * NP] = v[x].x * v[x].y;
         });
-        sfor<G>([&](auto I) {
-            constexpr int x = g0 + decltype(I)::value;
-            q[x * NP * NP] = prod[decltype(I)::value];
+    } else {
+        // accumulator read-modify-write as in g_inv_x: unconditional loads, one group in FP32,
+        // fenced groups in FP64
+        constexpr int G = sizeof(T) == 4 ? NP : (NP % 8 == 0) ? 8 : (NP % 6 == 0 ? 6 : NP);
+        sfor<NP / G>([&](auto gI) {
+            constexpr int g0 = decltype(gI)::value * G;
+            T prod[G];
+            sfor<G>([&](auto I) { prod[decltype(I)::value] = q[(g0 + decltype(I)::value) * NP * NP]; });
+            sfor<G>([&](auto I) {
+                constexpr int x = g0 + decltype(I)::value;
+                q[x * NP * NP] = prod[decltype(I)::value] + v[x].x * v[x].y;
+            });
+            __builtin_amdgcn_sched_barrier(0);
         });
-        __builtin_amdgcn_sched_barrier(0);
-    });
+    }
 }
 
 // per term, z and y fused: one wave per (cell, kx) plane.  Lanes ky < n compute Z over kz,
