@@ -187,13 +187,17 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
 
     // ---- forward transform: row x = i over y, then columns over x ----
     // coalesced load: lane i reads element y = i of every row; the cell's block turns
-    // the columns into rows
+    // the columns into rows.  The loads are unconditional (a past-the-end cell reads cell 0
+    // and discards it): a load under the `live` condition is not speculated, and each then
+    // waited for the memory before the next was issued.
     cx<R> z[N];
     {
         const double* fc = A.f + (live ? cell : 0) * (int64_t)NN + i;
+        double fv[N];
+        sfor<N>([&](auto xI) { fv[decltype(xI)::value] = fc[decltype(xI)::value * N]; });
         sfor<N>([&](auto xI) {
             constexpr int x = decltype(xI)::value;
-            const R v = live ? (R)fc[x * N] : R(0);
+            const R v = live ? (R)fv[x] : R(0);
             if constexpr (sizeof(R) == 4) blk[x * RS + i] = cx<float>{v, 0.0f};
             else blk[x * RS + i] = v;
         });
