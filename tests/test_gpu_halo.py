@@ -61,7 +61,8 @@ class Slabs:
 
 @pytest.mark.parametrize("n,sizes,bc_xy", [(4, (3, 1, 3), (fks.BC_DIRICHLET, fks.BC_PERIODIC)),
                                            (5, (2, 2, 1, 2), (fks.BC_PERIODIC, fks.BC_DIRICHLET)),
-                                           (6, (7,), (fks.BC_PERIODIC, fks.BC_PERIODIC))])
+                                           (6, (7,), (fks.BC_PERIODIC, fks.BC_PERIODIC)),
+                                           (16, (1, 2), (fks.BC_DIRICHLET, fks.BC_DIRICHLET))])
 def test_slabs_reproduce_the_whole_grid_transport(n, sizes, bc_xy):
     T, nx, ny = 2.0, 3, 2
     nz = sum(sizes)
