@@ -215,8 +215,15 @@ def main():
     fb = torch.empty_like(f0)
     q = torch.empty_like(f0)
 
-    plan = fks.Plan(fks.Desc(n=N_V, T=T_BOX, gamma=1.0, n_polar=N_POLAR, n_azim=N_AZIM,
-                             precision=fks.PREC_F32_FIX64))
+    desc = fks.Desc(n=N_V, T=T_BOX, gamma=1.0, n_polar=N_POLAR, n_azim=N_AZIM, precision=fks.PREC_F32_FIX64)
+    plan = fks.Plan(desc)
+    # a second plan of the same configuration, timed: the first one of the process also loads
+    # the library's code objects
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
+    with fks.Plan(desc):
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t_plan) * 1e3   # directions, radial terms, device tables
     assert plan.info.fused == 1
     ws = fks.collide_batch([(plan, fa, q, None, NCELL, 0.0)])   # untimed parity run (Q_c)
     torch.cuda.synchronize()
@@ -641,6 +648,10 @@ def main():
                      "call_ms": round(avg_call_ms, 4), "flops_per_cell": plan.info.flops_per_cell,
                      "source_hash": _fused_source_hash()},
         "cpu_baseline": cpu,
+        "plan": {"ms_create": round(plan_ms, 3), "table_bytes": plan.info.table_bytes,
+                 "what": "fks_plan_create of the timed configuration (host rule and radial terms, FP64 "
+                         "device tables, FP32 copies, loss table, Gram matrix), once per configuration, "
+                         "outside the timed steps"},
         "fp64_path": fp64,
         "parity": parity,
         "bgk": bgk_line,
