@@ -132,7 +132,9 @@ typedef struct {
  */
 fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan** out);
 
-/* Frees the plan's device memory (synchronises the device first).  NULL is a no-op. */
+/* Frees the plan's device memory (on the device the plan was created on; hipFree
+ * waits for work pending there, so no explicit synchronisation is made).  The caller
+ * must not destroy a plan that another host thread is using.  NULL is a no-op. */
 fks_status fks_plan_destroy(fks_plan* plan);
 
 /* Fills *info (host).  FKS_ERR_INVALID on NULL. */

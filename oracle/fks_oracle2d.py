@@ -130,11 +130,12 @@ def synthesize2(gh: np.ndarray, n: int, T: float) -> np.ndarray:
     return np.fft.ifft2(gh * _phase2(n, T), axes=(-2, -1)) * float(n) ** 2
 
 
-def collide2_fast64(f: np.ndarray, p: Plan2, parts: bool = False):
+def collide2_fast64(f: np.ndarray, p: Plan2, parts: bool = False, zero_nyquist: bool = True):
     """Fast form Q = sum_p omega a_p b_p - f_N F^{-1}(L fhat), a_p = F^{-1}(alpha_p fhat),
-    b_p = F^{-1}(alpha'_p fhat) (Section 3.3, eqs. ode and dfor0), FP64."""
+    b_p = F^{-1}(alpha'_p fhat) (Section 3.3, eqs. ode and dfor0), FP64.
+    ``zero_nyquist = False`` keeps the -n/2 modes (then Q is the real part)."""
     n, T = p.n, p.T
-    fh = spectrum2(f, n, T)
+    fh = spectrum2(f, n, T, zero_nyquist=zero_nyquist)
     fN = synthesize2(fh, n, T).real
     a = synthesize2(p.alpha * fh, n, T).real
     b = synthesize2(p.alphap * fh, n, T).real
@@ -203,19 +204,21 @@ def maxwellian2(n: int, T: float, rho: float, u, theta: float) -> np.ndarray:
     return rho / (2.0 * math.pi * theta) * np.exp(-r2 / (2.0 * theta))
 
 
-def bkw2d(n: int, T: float, t: float) -> np.ndarray:
+def bkw2d(n: int, T: float, t: float, node_offset: float = 0.0) -> np.ndarray:
     """Exact BKW solution of Test 1.1 (eq. Jngb): S = 1 - exp(-t/8)/2,
-    f = exp(-v^2/(2S)) [2S - 1 + (1 - S) v^2 / (2S)] / (2 pi S^2)."""
-    v = velocity_grid2(n, T)
+    f = exp(-v^2/(2S)) [2S - 1 + (1 - S) v^2 / (2S)] / (2 pi S^2), sampled at
+    v_j = -T + (j + node_offset) dv (node_offset = 1/2: cell-centred nodes)."""
+    v = velocity_grid2(n, T) + node_offset * (2.0 * T / n)
     vx, vy = np.meshgrid(v, v, indexing="ij")
     v2 = vx * vx + vy * vy
     S = 1.0 - 0.5 * math.exp(-t / 8.0)
     return np.exp(-v2 / (2.0 * S)) * (2.0 * S - 1.0 + (1.0 - S) * v2 / (2.0 * S)) / (2.0 * math.pi * S * S)
 
 
-def bkw2d_initial(n: int, T: float) -> np.ndarray:
-    """Initial condition of Test 1.1 (eq. BKW): f(v, 0) = v^2 / pi exp(-v^2)."""
-    v = velocity_grid2(n, T)
+def bkw2d_initial(n: int, T: float, node_offset: float = 0.0) -> np.ndarray:
+    """Initial condition of Test 1.1 (eq. BKW): f(v, 0) = v^2 / pi exp(-v^2), sampled at
+    v_j = -T + (j + node_offset) dv."""
+    v = velocity_grid2(n, T) + node_offset * (2.0 * T / n)
     vx, vy = np.meshgrid(v, v, indexing="ij")
     v2 = vx * vx + vy * vy
     return v2 / math.pi * np.exp(-v2)
@@ -245,20 +248,27 @@ def loss_frequency2_exact(R: float, c0: float = 1.0 / (2.0 * math.pi)) -> float:
 
 
 def test11_errors(n: int, T: float, A: int = 8, dt: float = 0.02, t_final: float = 10.0,
-                  conserve: bool = True):
+                  conserve: bool = True, R: float = 0.0, node_offset: float = 0.0,
+                  zero_nyquist: bool = True):
     """Test 1.1 of Section 5.1: explicit Euler steps of the space-homogeneous
     equation from f(v, 0) = v^2/pi exp(-v^2), with the conservation projection
     applied to each Q if ``conserve``; returns the discrete relative L1 and L2
-    errors against the exact solution at t_final."""
-    p = make_plan2(n, T, A)
-    f = bkw2d_initial(n, T)
+    errors against the exact solution at t_final.
+
+    R <= 0 takes the default radius.  ``node_offset`` places the samples of the
+    datum and of the exact solution at v_j = -T + (j + node_offset) dv; the
+    operator acts on the sample vector exactly as on the node grid (the same
+    transforms and tables: the sample positions are a property of the data, which
+    the paper does not state)."""
+    p = make_plan2(n, T, A, R=R)
+    f = bkw2d_initial(n, T, node_offset)
     steps = int(round(t_final / dt))
     for _ in range(steps):
-        Q = collide2_fast64(f, p)
+        Q = collide2_fast64(f, p, zero_nyquist=zero_nyquist)
         if conserve:
             Q = conserve2_Q(Q, n, T)
         f = f + dt * Q
-    ex = bkw2d(n, T, steps * dt)
+    ex = bkw2d(n, T, steps * dt, node_offset)
     l1 = float(np.sum(np.abs(f - ex)) / np.sum(np.abs(ex)))
     l2 = float(np.sqrt(np.sum((f - ex) ** 2) / np.sum(ex ** 2)))
     return l1, l2

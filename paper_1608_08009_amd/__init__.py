@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -246,6 +247,10 @@ class Plan:
         self.close()
 
     def __del__(self):
+        # at interpreter exit the HIP runtime (or a profiler wrapped around it) may already be
+        # finalised: a plan still open then is left to the process teardown
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

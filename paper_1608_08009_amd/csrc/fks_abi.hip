@@ -483,10 +483,14 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
 
 fks_status fks_plan_destroy(fks_plan* p) {
     if (!p) return FKS_OK;
-    fks_status st = FKS_OK;
-    if (hipDeviceSynchronize() != hipSuccess) st = FKS_ERR_DEVICE;
+    // the plan's memory lives on the device it was created on; hipFree itself waits for
+    // work still pending on that device
+    int cur = 0;
+    const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != p->device;
+    if (switch_dev && hipSetDevice(p->device) != hipSuccess) return FKS_ERR_DEVICE;
     plan_free(p);
-    return st;
+    if (switch_dev) (void)hipSetDevice(cur);
+    return FKS_OK;
 }
 
 fks_status fks_plan_query(const fks_plan* p, fks_plan_info* info) {

@@ -162,9 +162,10 @@ def two_maxwellian_cells_2d(n: int, T: float, ncell: int, seed_offset: int = 20)
     return out
 
 
-def bkw2d_initial(n: int, T: float) -> np.ndarray:
-    """Initial datum of the two-dimensional BKW test: |v|^2/pi exp(-|v|^2) on the n^2 grid."""
-    v = velocity_nodes(n, T)
+def bkw2d_initial(n: int, T: float, node_offset: float = 0.0) -> np.ndarray:
+    """Initial datum of the two-dimensional BKW test: |v|^2/pi exp(-|v|^2) on the n^2 grid,
+    sampled at v_j = -T + (j + node_offset) 2T/n (node_offset = 1/2: cell centres)."""
+    v = velocity_nodes(n, T) + node_offset * (2.0 * T / n)
     v2 = v[:, None] ** 2 + v[None, :] ** 2
     return v2 / math.pi * np.exp(-v2)
 

@@ -107,6 +107,37 @@ def test_test11_trajectory_matches_oracle(prec, tol):
     assert abs(l1 - l1_or) <= 1e-3 * l1_or + tol
 
 
+@pytest.mark.parametrize("prec", [fks.PREC_F64, fks.PREC_F32_FIX64])
+def test_test11_table1_on_the_gpu(prec):
+    # Table 1 of Test 1.1 (Section 5.1) through the library: cell-centred samples, R = T/sqrt 2,
+    # explicit Euler at dt = 0.01 to t = 10, 8 angles.  The trajectory follows the oracle's, and
+    # the six printed L1 / L2 errors are reproduced within a factor 2
+    import math
+    import os
+    golden = os.path.join(os.path.dirname(__file__), "golden", "table1_test11_bkw2d.txt")
+    rows = [ln.split() for ln in open(golden) if ln.strip() and not ln.startswith("#")]
+    dt, steps, A = 0.01, 1000, 8
+    for n_s, T_s, l1p_s, l2p_s in rows:
+        n, T, l1p, l2p = int(n_s), float(T_s), float(l1p_s), float(l2p_s)
+        R = T / math.sqrt(2.0)
+        f0 = synth.bkw2d_initial(n, T, node_offset=0.5)
+        with fks.Plan(fks.desc2d(n, T, A, prec, R=R)) as plan:
+            f = _dev(f0[None])
+            for _ in range(steps):
+                fks.collide(plan, f, f_out=f, dt_over_tau=dt)
+            torch.cuda.synchronize()
+            got = f[0].cpu().numpy()
+        ex = O2.bkw2d(n, T, steps * dt, node_offset=0.5)
+        l1 = float(np.sum(np.abs(got - ex)) / np.sum(np.abs(ex)))
+        l2 = float(np.sqrt(np.sum((got - ex) ** 2) / np.sum(ex ** 2)))
+        l1_or, l2_or = O2.test11_errors(n, T, A, dt=dt, R=R, node_offset=0.5)
+        tol = 1e-9 if prec == fks.PREC_F64 else 2e-2
+        print(f"test 1.1 n={n} precision={prec}: L1 {l1:.3e} (oracle {l1_or:.3e}, printed {l1p:.1e}), "
+              f"L2 {l2:.3e} (oracle {l2_or:.3e}, printed {l2p:.1e})", flush=True)
+        assert abs(l1 - l1_or) <= tol * l1_or and abs(l2 - l2_or) <= tol * l2_or
+        assert l1p / 2 <= l1 <= 2 * l1p and l2p / 2 <= l2 <= 2 * l2p
+
+
 def test_mixed_2d_and_3d_batch():
     # one fks_collide_batch call with a 2D and a 3D segment
     n2, T2, n3, T3 = 32, 9.0, 16, 8.0

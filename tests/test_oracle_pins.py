@@ -15,6 +15,67 @@ import oracle as O
 import synth
 
 
+# -- eqs. FU, FC: the normalisation and phase of the spectrum against a closed form --
+
+def _gaussian_coefficients(n, T, theta, u):
+    """Fourier coefficients of eq. FC on [-T, T)^3 for the drifting Maxwellian of
+    temperature theta, sampled at the nodes: per axis (1/2T) sum_m exp(-theta xi^2/2 - i xi u)
+    with xi = kappa (k + m n) (the continuous transform of the Gaussian plus its aliases, by
+    the Poisson summation formula; the tails beyond the box are below 1e-25 here)."""
+    kappa = math.pi / T
+    k = np.fft.fftfreq(n, d=1.0 / n).round()
+    out = []
+    for a in range(3):
+        s = np.zeros(n, dtype=np.complex128)
+        for m in range(-4, 5):
+            xi = kappa * (k + m * n)
+            s += np.exp(-theta * xi * xi / 2 - 1j * xi * u[a])
+        out.append(s / (2 * T))
+    return out[0][:, None, None] * out[1][None, :, None] * out[2][None, None, :]
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_spectrum_matches_closed_form(n):
+    # eq. FC on the node grid: fhat_k = n^-3 sum_j f_j exp(-i kappa k.v_j).  For a centred
+    # Maxwellian (theta = 1, T = 8) the coefficients are real and positive,
+    # (2T)^-3 exp(-kappa^2 |k|^2 / 2) plus aliases; a drift u multiplies them by
+    # exp(-i kappa k.u).  Catches a dropped (-1)^k phase of the nodes v_0 = -T, a missing n^-3,
+    # a conjugated exponent (the sign of the drift phase) and a transposed axis (u differs
+    # per axis)
+    T = 8.0
+    for u in ((0.0, 0.0, 0.0), (0.7, -0.4, 0.25)):
+        # the periodic extension of the Maxwellian (images shifted by 2T): the closed form is then
+        # exact up to rounding, without the 1e-12 tail that leaves the box
+        f = sum(synth.maxwellian(n, T, 1.0, (u[0] + 2 * T * a, u[1] + 2 * T * b, u[2] + 2 * T * c), 1.0)
+                for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1))
+        got = O.spectrum(f, n, T, zero_nyquist=False)
+        ref = _gaussian_coefficients(n, T, 1.0, u)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+        if u == (0.0, 0.0, 0.0):
+            assert np.all(ref.real > 0) and np.max(np.abs(got.imag)) <= 1e-16
+    # Nyquist zeroing removes exactly the modes with a component -n/2
+    got = O.spectrum(f, n, T)
+    h = n // 2
+    mask = np.ones((n, n, n), bool)
+    mask[h], mask[:, h], mask[:, :, h] = False, False, False
+    assert np.all(got[~mask] == 0) and np.max(np.abs(got[mask] - ref[mask])) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_synthesize_matches_plane_waves():
+    # eq. FU on the grid: a single coefficient at k0 synthesises exp(i kappa k0.v_j); catches a
+    # sign of the exponent, a missing n^3 and an axis order different from [x][y][z]
+    n, T = 8, 3.0
+    v = O.velocity_grid(n, T)
+    kappa = math.pi / T
+    for k0 in ((1, 0, 0), (0, 2, -3), (-1, 3, 1)):
+        gh = np.zeros((n, n, n), dtype=np.complex128)
+        gh[k0[0] % n, k0[1] % n, k0[2] % n] = 1.0
+        got = O.synthesize(gh, n, T)
+        ref = np.exp(1j * kappa * (k0[0] * v[:, None, None] + k0[1] * v[None, :, None]
+                                   + k0[2] * v[None, None, :]))
+        assert np.max(np.abs(got - ref)) <= 1e-14
+
+
 # -- P1: radial functions against their integral definitions (Section 3.3) --
 
 @pytest.mark.parametrize("R", [1.3, 3.6247])
