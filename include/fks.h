@@ -211,6 +211,30 @@ fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* worksp
                              size_t ws_bytes, void* hip_stream);
 
 /*
+ * fks_collide_batch without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same segments, kernels, schedules and
+ * results (bit for bit) as fks_collide_batch with a caller workspace; the
+ * workspace is instead a static device array of FKS_STATIC_WORKSPACE_BYTES that
+ * the library holds on every GPU it runs on until the process ends (its address
+ * is looked up once per device, at plan creation).  Nothing is allocated or
+ * freed and no allocating library routine is called.
+ *   Segments whose workspace (fks_workspace_size) exceeds
+ *   FKS_STATIC_WORKSPACE_BYTES are rejected with FKS_ERR_INVALID before anything
+ *   is enqueued.  64 MiB holds the fused path's largest layout at n = 32 (one
+ *   128 KiB spectrum slot per resident workgroup) and the small-batch pair layout
+ *   up to about 170 cells of 32^3; the multi-pass path (FP64, n = 48) needs more
+ *   for large batches and is then rejected.
+ *   Every call on one GPU shares that GPU's array and leaves its contents behind
+ *   (the kernels write every workspace location before reading it, so nothing
+ *   needs clearing): calls that overlap on one GPU, on different streams or from
+ *   different host threads, race and must be serialised by the caller.
+ * Errors: as fks_collide_batch.
+ */
+#define FKS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+fks_status fks_collide_batch_static(const fks_segment* segs, int32_t nseg, void* hip_stream);
+
+/*
  * Autotuner.  For each segment, times the schedules fks_collide_batch can use
  * for it and keeps the fastest in the segment's plan, keyed by ncell: for
  * fused plans one workgroup per cell or pairs of workgroups per cell; for the

@@ -45,8 +45,10 @@ EXPORTED = [
     "fks_host_sphere_rule", "fks_host_radial_terms", "fks_profile_enable", "fks_profile_last",
     "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
     "fks_numeric_status", "fks_autotune_workspace_size", "fks_autotune",
-    "fks_halo_size", "fks_halo_pack", "fks_transport_shift_slab",
+    "fks_halo_size", "fks_halo_pack", "fks_transport_shift_slab", "fks_collide_batch_static",
 ]
+
+STATIC_WORKSPACE_BYTES = 64 << 20   # FKS_STATIC_WORKSPACE_BYTES
 
 
 class PlanDesc(C.Structure):
@@ -106,6 +108,7 @@ def lib() -> C.CDLL:
     L.fks_plan_copy_tables.argtypes = [vp, vp, vp]
     L.fks_workspace_size.argtypes = [C.POINTER(Segment), i32, C.POINTER(sz)]
     L.fks_collide_batch.argtypes = [C.POINTER(Segment), i32, vp, sz, vp]
+    L.fks_collide_batch_static.argtypes = [C.POINTER(Segment), i32, vp]
     L.fks_moments.argtypes = [vp, i64, i32, dbl, vp, vp]
     L.fks_conserve.argtypes = [vp, vp, i64, i32, dbl, vp]
     L.fks_transport_shift.argtypes = [vp, vp, C.POINTER(SpaceDesc), i32, dbl, dbl, vp, vp, vp]
@@ -324,6 +327,23 @@ def collide_batch(segments, workspace=None, stream=None):
     _check(lib().fks_collide_batch(arr, len(segments), C.c_void_p(_ptr(workspace)), workspace.numel(),
                                    C.c_void_p(_stream_ptr(stream))), "fks_collide_batch")
     return workspace
+
+
+def collide_batch_static(segments, stream=None) -> None:
+    """fks_collide_batch_static: fks_collide_batch with the library's static per-GPU
+    workspace (no allocation anywhere in the call).  Raises FksError(FKS_ERR_INVALID) when
+    the segments need more than STATIC_WORKSPACE_BYTES.  Calls that overlap on one GPU
+    share that workspace and race."""
+    for item in segments:
+        plan, f, q_out, f_out, ncell, dt, f_base = _segment_fields(item)
+        nn = ncell * plan.cell_size
+        _require_device_f64(f, "f", nn)
+        _require_device_f64(q_out, "q_out", nn)
+        _require_device_f64(f_out, "f_out", nn)
+        _require_device_f64(f_base, "f_base", nn)
+    arr = _segments(segments)
+    _check(lib().fks_collide_batch_static(arr, len(segments), C.c_void_p(_stream_ptr(stream))),
+           "fks_collide_batch_static")
 
 
 def autotune(segments, workspace=None, stream=None):

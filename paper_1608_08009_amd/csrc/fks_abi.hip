@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -276,6 +277,35 @@ static fks_status resolve_desc(const fks_plan_desc* in, fks_plan_desc* out) {
     return FKS_OK;
 }
 
+// Workspace of fks_collide_batch_static: a file-scope device array, one copy per GPU,
+// held from the code object's load until the process ends.  In host code its name is
+// a host-side stand-in, not a device address: the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current (at plan
+// creation, this library's set-up call, else at the first static call on the device)
+// and kept here; only that address is handed to kernels.
+__device__ __align__(256) unsigned char scratch[FKS_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// device address of the current device's copy of `scratch`
+static fks_status static_workspace(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FKS_ERR_DEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return FKS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FKS_ERR_DEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FKS_OK;
+}
+
 }  // namespace fks
 
 using namespace fks;
@@ -405,6 +435,11 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
     p->desc = d;
     const int n = d.n;
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FKS_ERR_DEVICE; }
+    void* static_ws = nullptr;   // set-up of fks_collide_batch_static's workspace on this device
+    if ((st = static_workspace(&static_ws)) != FKS_OK) {
+        delete p;
+        return st;
+    }
     if (d.flags & FKS_FLAG_NUMERIC_GUARD) {
         const unsigned long long none = ~0ull;
         if (hipMalloc(&p->d_guard, sizeof(none)) != hipSuccess) {
@@ -591,17 +626,20 @@ fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* byt
     return FKS_OK;
 }
 
-fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
-                             void* hip_stream) {
+// Segments of one call, validated; the workspace the largest of them needs.
+static fks_status batch_need(const fks_segment* segs, int32_t nseg, size_t* need) {
     if (nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
-    size_t need = 0;
+    *need = 0;
     for (int i = 0; i < nseg; ++i) {
         fks_status st = check_segment(segs[i]);
         if (st != FKS_OK) return st;
-        need = std::max(need, segment_ws(segs[i]));
+        *need = std::max(*need, segment_ws(segs[i]));
     }
-    if (need > 0 && (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255u))) return FKS_ERR_INVALID;
-    hipStream_t s = (hipStream_t)hip_stream;
+    return FKS_OK;
+}
+
+static fks_status batch_launch(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
+                               hipStream_t s) {
     for (int i = 0; i < nseg; ++i) {
         const fks_segment& g = segs[i];
         if (g.ncell == 0) continue;
@@ -611,6 +649,25 @@ fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* worksp
         if (e != hipSuccess) return FKS_ERR_DEVICE;
     }
     return FKS_OK;
+}
+
+fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
+                             void* hip_stream) {
+    size_t need = 0;
+    fks_status st = batch_need(segs, nseg, &need);
+    if (st != FKS_OK) return st;
+    if (need > 0 && (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255u))) return FKS_ERR_INVALID;
+    return batch_launch(segs, nseg, workspace, ws_bytes, (hipStream_t)hip_stream);
+}
+
+fks_status fks_collide_batch_static(const fks_segment* segs, int32_t nseg, void* hip_stream) {
+    size_t need = 0;
+    fks_status st = batch_need(segs, nseg, &need);
+    if (st != FKS_OK) return st;
+    if (need > FKS_STATIC_WORKSPACE_BYTES) return FKS_ERR_INVALID;
+    void* ws = nullptr;
+    if (need > 0 && (st = static_workspace(&ws)) != FKS_OK) return st;
+    return batch_launch(segs, nseg, ws, need > 0 ? FKS_STATIC_WORKSPACE_BYTES : 0, (hipStream_t)hip_stream);
 }
 
 // Candidate schedules of one segment: the two fused decompositions, or cells per

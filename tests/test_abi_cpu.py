@@ -214,3 +214,17 @@ def test_halo_sizes_and_rejections_on_the_host():
         assert L.fks_transport_shift_slab(fake_a, fake_b, C.byref(sp), n, T, 0.1, C.c_void_p(off.ctypes.data),
                                           below, above, None, None) == fks.FKS_ERR_INVALID
         assert not off.any()
+
+
+def test_static_workspace_size_and_host_validation():
+    # the binding's constant is the header's; validation needs no device
+    text = open(os.path.join(ROOT, "include", "fks.h")).read()
+    m = re.search(r"#define FKS_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == fks.STATIC_WORKSPACE_BYTES
+    L = fks.lib()
+    assert L.fks_collide_batch_static(None, -1, None) == fks.FKS_ERR_INVALID
+    assert L.fks_collide_batch_static(None, 1, None) == fks.FKS_ERR_INVALID
+    assert L.fks_collide_batch_static(None, 0, None) == fks.FKS_OK
+    seg = (fks.Segment * 1)()
+    seg[0] = fks.Segment(None, None, None, None, 4, 0.0, None)   # no plan
+    assert L.fks_collide_batch_static(seg, 1, None) == fks.FKS_ERR_INVALID
