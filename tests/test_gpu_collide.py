@@ -59,6 +59,20 @@ def _oracle_qc(f, op, ratios=False):
     return (np.stack(qs), np.array(rs)) if ratios else np.stack(qs)
 
 
+def _loss_ratios(f, qc, op, chunk=64):
+    """||Q^-|| / ||Q_c|| per cell: the oracle's loss term f_N F^{-1}(L fhat) of every cell of f
+    (transforms only, no gain terms), against a given Q_c."""
+    out = []
+    for c0 in range(0, f.shape[0], chunk):
+        fc = f[c0:c0 + chunk]
+        fh = O.spectrum(fc, op.n, op.T)
+        loss = O.synthesize(fh, op.n, op.T).real * O.synthesize(op.loss * fh, op.n, op.T).real
+        num = np.sqrt(np.sum(loss.reshape(fc.shape[0], -1) ** 2, axis=1))
+        den = np.sqrt(np.sum(qc[c0:c0 + chunk].reshape(fc.shape[0], -1) ** 2, axis=1))
+        out.append(num / den)
+    return np.concatenate(out)
+
+
 def _check_f32(q, ref, ratio):
     agg = _rel(q, ref)
     assert agg <= 1e-5, agg
@@ -307,7 +321,13 @@ def test_one_workgroup_per_cell_matches_pairs_fp64_and_oracle(n):
     err = torch.sqrt(torch.sum((q - q64) ** 2, dim=(1, 2, 3)) / torch.sum(q64 ** 2, dim=(1, 2, 3)))
     agg = float(torch.sqrt(torch.sum((q - q64) ** 2) / torch.sum(q64 ** 2)))
     assert agg <= 1e-5, agg
-    assert float(err.max()) <= 1e-3, (int(err.argmax()), float(err.max()))
+    # every cell to the cancellation-aware FP32 bound; the FP64 path stands in for the
+    # oracle here (it matches it to 1e-12, checked on the sampled cells below and in the
+    # FP64 tests), and the oracle gives each cell's loss term
+    ratio_all = _loss_ratios(f.cpu().numpy(), q64.cpu().numpy(), _oplan(n, T_BOX, 1.0, 8, 4, 0))
+    bound = 1.5e-6 * (1.0 + ratio_all)
+    bad = np.nonzero(err.cpu().numpy() > bound)[0]
+    assert bad.size == 0, [(int(c), float(err[c]), float(ratio_all[c])) for c in bad[:5]]
     assert _conservation_torch(q, n, T_BOX) <= 1e-12
     sample = [0, G - 1, G, ncell - 1]
     fh = f[sample].cpu().numpy()
