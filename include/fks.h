@@ -111,13 +111,14 @@ typedef struct {
     double  R;                 /* truncation radius actually used */
     double  c_gamma;           /* kernel constant actually used */
     int32_t precision;         /* fks_precision */
-    int32_t fused;             /* 1 if fks_collide_batch uses the fused kernels (FP32, dim 3, n <= 32) */
+    int32_t fused;             /* 1 if fks_collide_batch uses the fused kernels (FP32, dim 3, n in
+                                  {8, 16, 24, 32, 48}; at n = 48 three workgroups per cell) */
     size_t  table_bytes;       /* device bytes held by the plan */
     double  flops_per_cell;    /* algorithmic flops of one Q evaluation: (2J'+2) 2.5 N log2 N + 7J' N + 3N,
                                   N = n^3 (n^2 for dim 2), J' = J - 1 (a real FFT counts 2.5 N log2 N);
                                   the de-aliased variant counts its zero-padded transforms instead */
     int32_t dim;               /* velocity dimension (2 or 3) */
-    int32_t fused_grid;        /* workgroups the fused kernel keeps resident (0 if not fused) */
+    int32_t fused_grid;        /* workgroups the fused terms kernel keeps resident (0 if not fused) */
 } fks_plan_info;
 
 /*
@@ -203,6 +204,14 @@ fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* byt
  * used concurrently by another call.  No device allocation, host
  * synchronisation or memset happens inside, so the call can be captured in a
  * HIP graph.  Results are deterministic (no floating-point atomics).
+ *   Launch groups: segments of fused FP32 plans (fks_plan_info.fused) that share
+ *   n, two or more in one call (up to 16 per group), run together: at n <= 32 one
+ *   work queue whose items are a cell's terms or a range of them (cells with many
+ *   terms are cut into ranges so that items have similar lengths; longest
+ *   first), FP32 partial sums, then one FP64 fix over all the group's cells; at
+ *   n = 48 one launch of the three-workgroup kernel over all their cells.  Other
+ *   segments run alone, in call order.  The grouping depends only on the
+ *   segments' plans and sizes, so results are reproducible call to call.
  * Errors: FKS_ERR_INVALID (NULL plan/f, both outputs NULL, ncell < 0,
  * misaligned arrays, small or misaligned workspace), FKS_ERR_DEVICE (launch
  * failure).
@@ -243,8 +252,9 @@ fks_status fks_collide_batch_static(const fks_segment* segs, int32_t nseg, void*
  * the work arrays stays in the on-chip caches, and the consecutive terms per
  * launch of the per-term kernels (1, 2 or 4; not for FKS_FLAG_DEALIAS), which
  * trades launches and accumulator traffic for work-array space.  Later fks_workspace_size and
- * fks_collide_batch calls with the same (plan, ncell) use the kept schedule;
- * other sizes keep the built-in cost model.  Schedules change the summation
+ * fks_collide_batch calls with the same (plan, ncell) use the kept schedule when
+ * the segment runs alone (not in a work queue with other segments of its n, see
+ * fks_collide_batch); other sizes keep the built-in cost model.  Schedules change the summation
  * order of the FP32 partial sums only, never the operator.
  *   Each segment is evaluated several times (its outputs are overwritten): its
  *   f_out must not overlap f or f_base.  workspace: at least

@@ -251,10 +251,11 @@ class Plan:
 
     def __del__(self):
         # at interpreter exit the HIP runtime (or a profiler wrapped around it) may already be
-        # finalised: a plan still open then is left to the process teardown
-        if sys.is_finalizing():
-            return
+        # finalised: a plan still open then is left to the process teardown (module globals such
+        # as sys may already be gone, hence the broad guard)
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfks.so")
 
-SOURCES = ["fks_abi.hip", "fks_tables.hip", "fks_generic.hip", "fks_fused.hip", "fks_aux.hip", "fks_2d.hip", "fks_bgk.hip"]
+SOURCES = ["fks_abi.hip", "fks_tables.hip", "fks_generic.hip", "fks_fused.hip", "fks_fused48.hip", "fks_aux.hip", "fks_2d.hip", "fks_bgk.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -614,41 +614,79 @@ static size_t segment_ws(const fks_segment& s) {
     return s.plan->fused ? fused_workspace_bytes(s.plan, s.ncell) : generic_workspace_bytes(s.plan, s.ncell);
 }
 
-fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes) {
-    if (!bytes || nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
-    size_t mx = 0;
-    for (int i = 0; i < nseg; ++i) {
-        fks_status st = check_segment(segs[i]);
-        if (st != FKS_OK) return st;
-        mx = std::max(mx, segment_ws(segs[i]));
-    }
-    *bytes = mx;
-    return FKS_OK;
+
+// Launch groups of one call.  Fused 3D segments that share n, two or more of them, go
+// through one work queue (up to fused_queue_max_segments() per queue; at n = 48 the
+// three-workgroup kernel over all their cells), so that small segments fill the device
+// together; every other segment runs alone, in call order.  Groups run one after another on the call's stream and share the
+// workspace.
+struct LaunchGroup {
+    std::vector<const fks_segment*> segs;
+    bool queue = false;
+};
+
+static bool queueable(const fks_segment& g) {
+    return g.ncell > 0 && g.plan->dim == 3 && g.plan->fused;
 }
 
-// Segments of one call, validated; the workspace the largest of them needs.
+static std::vector<LaunchGroup> batch_groups(const fks_segment* segs, int32_t nseg) {
+    std::vector<LaunchGroup> out;
+    std::vector<bool> done(nseg, false);
+    for (int i = 0; i < nseg; ++i) {
+        if (done[i] || segs[i].ncell == 0) continue;
+        done[i] = true;
+        LaunchGroup g;
+        g.segs.push_back(&segs[i]);
+        if (queueable(segs[i])) {
+            for (int k = i + 1; k < nseg && (int)g.segs.size() < fused_queue_max_segments(); ++k) {
+                if (!done[k] && queueable(segs[k]) && segs[k].plan->desc.n == segs[i].plan->desc.n) {
+                    g.segs.push_back(&segs[k]);
+                    done[k] = true;
+                }
+            }
+            g.queue = g.segs.size() > 1;
+        }
+        out.push_back(std::move(g));
+    }
+    return out;
+}
+
+static size_t group_ws(const LaunchGroup& g) {
+    return g.queue ? fused_queue_workspace_bytes(g.segs.data(), (int)g.segs.size()) : segment_ws(*g.segs[0]);
+}
+
+// Segments of one call, validated; the workspace the largest launch group needs.
 static fks_status batch_need(const fks_segment* segs, int32_t nseg, size_t* need) {
     if (nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
     *need = 0;
     for (int i = 0; i < nseg; ++i) {
         fks_status st = check_segment(segs[i]);
         if (st != FKS_OK) return st;
-        *need = std::max(*need, segment_ws(segs[i]));
     }
+    for (const LaunchGroup& g : batch_groups(segs, nseg)) *need = std::max(*need, group_ws(g));
     return FKS_OK;
 }
 
 static fks_status batch_launch(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
                                hipStream_t s) {
-    for (int i = 0; i < nseg; ++i) {
-        const fks_segment& g = segs[i];
-        if (g.ncell == 0) continue;
-        hipError_t e = g.plan->dim == 2 ? collide_2d(g.plan, g, s)
-                       : g.plan->fused ? collide_fused(g.plan, g, workspace, ws_bytes, s)
-                                       : collide_generic(g.plan, g, workspace, ws_bytes, s);
+    for (const LaunchGroup& grp : batch_groups(segs, nseg)) {
+        hipError_t e = hipSuccess;
+        if (grp.queue) {
+            e = collide_fused_queue(grp.segs.data(), (int)grp.segs.size(), workspace, ws_bytes, s);
+        } else {
+            const fks_segment& g = *grp.segs[0];
+            e = g.plan->dim == 2 ? collide_2d(g.plan, g, s)
+                : g.plan->fused  ? collide_fused(g.plan, g, workspace, ws_bytes, s)
+                                 : collide_generic(g.plan, g, workspace, ws_bytes, s);
+        }
         if (e != hipSuccess) return FKS_ERR_DEVICE;
     }
     return FKS_OK;
+}
+
+fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes) {
+    if (!bytes) return FKS_ERR_INVALID;
+    return batch_need(segs, nseg, bytes);
 }
 
 fks_status fks_collide_batch(const fks_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes,
@@ -676,6 +714,7 @@ static std::vector<Schedule> schedule_candidates(const fks_segment& s) {
     std::vector<Schedule> c;
     if (s.ncell <= 0 || s.plan->dim == 2) return c;
     if (s.plan->fused) {
+        if (s.plan->desc.n == 48) return c;   // one decomposition (three workgroups per cell)
         c.push_back(Schedule{1, 0});
         c.push_back(Schedule{0, 0});
         return c;

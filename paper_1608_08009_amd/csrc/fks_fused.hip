@@ -59,6 +59,9 @@
 // exchange can reuse that block without a barrier.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "fks_common.hpp"
 
 namespace fks {
@@ -144,12 +147,62 @@ struct FusedArgs {
     unsigned long long* guard;   // numeric guard word, or null
 };
 
-// ONE = false: the pair kernel above (partials, then k_finish).  ONE = true: one
-// workgroup evaluates all terms of a cell and applies the FP64 fix and the update
-// itself (persistent loop over cells b, b + G, ...; the spectrum slot is per
-// workgroup and reused from cell to cell).
-template <int N, bool ONE>
-__global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
+// Work queue over several segments of one n (an uneven batch): an item is a range of
+// terms of one cell (cells with many terms are cut into nchunk ranges, so that no item
+// is much longer than the rest); workgroups take items from one counter, largest items
+// first.  Each item computes the cell's forward transform into the workgroup's slot,
+// evaluates its terms and writes its FP32 partial sum; k_finish_q then adds a cell's
+// partials and applies the FP64 fix.  Segments sit in the kernel arguments.
+constexpr int kMaxQSeg = 16;
+struct QSeg {
+    const double* f;        // [ncell][n^3]
+    const double* f_base;   // state of the update
+    double* q_out;
+    double* f_out;
+    const cx<float>* tab;   // the plan's balanced FP32 tables
+    const GridConst* gc;
+    unsigned long long* guard;
+    double dt;
+    int64_t item0;          // first item of the segment (items are cell-major, then range)
+    int64_t cell0;          // first cell of the segment in the finish grid
+    int64_t part0;          // first partial slot (slot = part0 + item - item0)
+    int J;
+    int nchunk;
+};
+struct QueueArgs {
+    QSeg seg[kMaxQSeg];
+    int nseg;
+    int64_t nitems;
+    int64_t ncell;          // cells of all segments
+    cx<float>* fh;          // [grid][n/2][n][n]: one spectrum slot per workgroup
+    float* part;            // [slots][n^3]
+    int* ctr;               // item counter, zero at launch
+};
+
+// the segment of a queue item (or of a finish cell): the last one whose first index is
+// at most i; compile-time indices keep the argument table in scalar registers
+template <bool BY_CELL>
+__device__ __forceinline__ QSeg qseg_of(const QueueArgs& Q, int64_t i) {
+    QSeg cur = Q.seg[0];
+    sfor<kMaxQSeg>([&](auto sI) {
+        constexpr int k = decltype(sI)::value;
+        if constexpr (k > 0) {
+            if (k < Q.nseg && (BY_CELL ? Q.seg[k].cell0 : Q.seg[k].item0) <= i) cur = Q.seg[k];
+        }
+    });
+    return cur;
+}
+
+// MODE 0: the pair kernel above (partials, then k_finish).  MODE 1: one workgroup
+// evaluates all terms of a cell and applies the FP64 fix and the update itself
+// (persistent loop over cells b, b + G, ...; the spectrum slot is per workgroup and
+// reused from cell to cell).  MODE 2: the work queue over several segments.
+template <int MODE>
+using TermsArgs = std::conditional_t<MODE == 2, QueueArgs, FusedArgs>;
+
+template <int N, int MODE>
+__global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) {
+    constexpr bool ONE = MODE == 1;
     constexpr int P = Cfg<N>::P;
     constexpr int NT = N * N / P;
     constexpr int HP = N / P;
@@ -161,23 +214,53 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
     constexpr int HS = (N / 2) * N * N;      // spectrum slot per cell
     __shared__ cx<float> lds[HP * BS];
     __shared__ double red[ONE ? 5 * (NT / 64) : 1];
+    __shared__ int64_t s_item;
 
     const int t = threadIdx.x;
     const int hi = t / N, lo = t % N;
     cx<float>* const blk = lds + hi * BS;   // this group's block
     // pairs of workgroups on one XCD: blocks b and b ^ 8
     const int b = blockIdx.x;
-    const int half = ONE ? 0 : (b >> 3) & 1;
-    const int pair = ONE ? b : (b & 7) | ((b >> 4) << 3);
-    const int64_t stride = ONE ? (int64_t)gridDim.x : (int64_t)A.npairs;
+    const int half = MODE == 0 ? (b >> 3) & 1 : 0;
+    const int pair = MODE == 0 ? (b & 7) | ((b >> 4) << 3) : b;
+    int64_t stride = 0;
+    if constexpr (MODE != 2) stride = ONE ? (int64_t)gridDim.x : (int64_t)A.npairs;
 
-    for (int64_t cell = pair, it = 0; cell < A.ncell; cell += stride, ++it) {
-        // split the terms in two; for odd J the extra term alternates between
-        // the halves so that the pair stays on the same cell
-        const int J0 = ONE ? A.J : (it & 1) ? A.J / 2 : (A.J + 1) / 2;
-        const int j_begin = half ? J0 : 0, j_end = half ? A.J : J0;
-        const double* fc = A.f + cell * (int64_t)N3;
-        cx<float>* const fh = A.fh + (ONE ? (int64_t)b : cell) * (int64_t)HS;
+    for (int64_t cell = pair, it = 0;; cell += stride, ++it) {
+        const double* fc;
+        const cx<float>* tab0;
+        int Jt, j_begin, j_end;
+        cx<float>* fh;
+        float* mine = nullptr;   // partial sum of MODE 0 and 2
+        if constexpr (MODE == 2) {
+            if (t == 0) s_item = atomicAdd(A.ctr, 1);
+            __syncthreads();
+            const int64_t item = __builtin_amdgcn_readfirstlane(s_item);
+            if (item >= A.nitems) break;
+            const QSeg g = qseg_of<false>(A, item);
+            const int64_t local = item - g.item0;
+            const int64_t c = local / g.nchunk;
+            const int k = (int)(local - c * g.nchunk);
+            Jt = g.J;
+            j_begin = (int)((int64_t)k * g.J / g.nchunk);
+            j_end = (int)((int64_t)(k + 1) * g.J / g.nchunk);
+            fc = g.f + c * (int64_t)N3;
+            tab0 = g.tab;
+            fh = A.fh + (int64_t)b * HS;
+            mine = A.part + (g.part0 + local) * (int64_t)N3;
+        } else {
+            if (cell >= A.ncell) break;
+            // split the terms in two; for odd J the extra term alternates between
+            // the halves so that the pair stays on the same cell
+            const int J0 = ONE ? A.J : (it & 1) ? A.J / 2 : (A.J + 1) / 2;
+            j_begin = half ? J0 : 0;
+            j_end = half ? A.J : J0;
+            Jt = A.J;
+            fc = A.f + cell * (int64_t)N3;
+            tab0 = A.tab;
+            fh = A.fh + (ONE ? (int64_t)b : cell) * (int64_t)HS;
+            if constexpr (MODE == 0) mine = A.part + (cell * 2 + half) * (int64_t)N3;
+        }
 
         // ---------------- forward transform ----------------
         cx<float> c[P][N];
@@ -246,7 +329,7 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
         // term ahead, during the last x transform of the previous term
         cx<float> pt[N / 2], pf[N / 2];
         auto load_own = [&](int jj) {
-            const char* tj = (const char*)(A.tab + (size_t)jj * H);
+            const char* tj = (const char*)(tab0 + (size_t)jj * H);
             const uint32_t oa8 = uint32_t(opaque(hi * N + lo)) * 8u;
             sfor<N / 2>([&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
@@ -255,9 +338,9 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
                 pf[kz] = *(const cx<float>*)((const char*)fh + (oa8 + zo));
             });
         };
-        load_own(min(j_begin, A.J - 1));
+        load_own(min(j_begin, Jt - 1));
         for (int j = j_begin; j < j_end; ++j) {
-            const cx<float>* tj = A.tab + (size_t)j * H;
+            const cx<float>* tj = tab0 + (size_t)j * H;
             cx<float> za[P][N];
             // Products Z = (a + i b) fhat.  Own pencil (hi, lo), kz in [0, n/2): from the
             // prefetched pt, pf; mirror pencil (-hi, -lo): loaded here in four groups of
@@ -422,7 +505,6 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(FusedArgs A) {
             });
         } else {
             // ---------------- partial sum (C layout: x, y = hi + HP p, z = lo) ----------------
-            float* mine = A.part + (cell * 2 + half) * (int64_t)N3;
             sfor<P>([&](auto pI) {
                 constexpr int p = decltype(pI)::value;
                 float* o = mine + opaque((hi + HP * p) * N + lo);
@@ -520,6 +602,89 @@ __global__ __launch_bounds__(finish_threads<N>()) void k_finish(FusedArgs A) {
     }
 }
 
+// Finish of the work queue: one workgroup per cell of all segments; sums the cell's nchunk
+// FP32 partials in FP64 (fixed order: bit-reproducible), then the FP64 fix and update
+// as in k_finish.
+template <int N>
+__global__ __launch_bounds__(finish_threads<N>()) void k_finish_q(QueueArgs Q) {
+    constexpr int N3 = N * N * N;
+    constexpr int VW = 4;
+    constexpr int FT = finish_threads<N>();
+    constexpr int V = N3 / (FT * VW);
+    constexpr int XS = FT * VW / (N * N);
+    __shared__ double red[5 * (FT / 64)];
+    const int t = threadIdx.x;
+    const int64_t gcell = blockIdx.x;
+    const QSeg g = qseg_of<true>(Q, gcell);
+    const int64_t c = gcell - g.cell0;
+    const float* p0 = Q.part + (g.part0 + c * g.nchunk) * (int64_t)N3;
+    const double h = g.gc->dv / g.gc->T;
+    const int z0 = (VW * t) % N, y = (VW * t / N) % N, x0 = VW * t / (N * N);
+    const double uy = -1.0 + y * h;
+    double uz[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) uz[k] = -1.0 + (z0 + k) * h;
+    double qv[V][VW];
+    double m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const int i = VW * t + k * FT * VW;
+        f4v a = __builtin_nontemporal_load((const f4v*)(p0 + i));
+        double acc[VW] = {(double)a[0], (double)a[1], (double)a[2], (double)a[3]};
+        for (int r = 1; r < g.nchunk; ++r) {
+            a = __builtin_nontemporal_load((const f4v*)(p0 + (int64_t)r * N3 + i));
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] += (double)a[e];
+        }
+        const double ux = -1.0 + (x0 + k * XS) * h;
+        const double rxy = fma(ux, ux, uy * uy);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const double q = acc[e];
+            qv[k][e] = q;
+            m[0] += q;
+            m[1] = fma(q, ux, m[1]);
+            m[2] = fma(q, uy, m[2]);
+            m[3] = fma(q, uz[e], m[3]);
+            m[4] = fma(q, fma(uz[e], uz[e], rxy), m[4]);
+        }
+    }
+    block_sum5<FT>(m, red);
+    if (g.guard && t == 0 && !isfinite(m[0] + m[1] + m[2] + m[3] + m[4])) atomicMin(g.guard, (unsigned long long)c);
+    double lam[5];
+    solve5(*g.gc, m, lam);
+    const int64_t base = c * (int64_t)N3 + VW * t;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const double ux = -1.0 + (x0 + k * XS) * h;
+        const double lx = fma(lam[4], fma(ux, ux, uy * uy), fma(lam[1], ux, fma(lam[2], uy, lam[0])));
+#pragma unroll
+        for (int e = 0; e < VW; ++e) qv[k][e] -= fma(lam[4], uz[e] * uz[e], fma(lam[3], uz[e], lx));
+    }
+    if (g.q_out) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            d2v* o = (d2v*)(g.q_out + base + k * FT * VW);
+            __builtin_nontemporal_store(d2v{qv[k][0], qv[k][1]}, o);
+            __builtin_nontemporal_store(d2v{qv[k][2], qv[k][3]}, o + 1);
+        }
+    }
+    if (g.f_out) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            const d2v* fi = (const d2v*)(g.f_base + base + k * FT * VW);
+            d2v* o = (d2v*)(g.f_out + base + k * FT * VW);
+            const d2v f0 = __builtin_nontemporal_load(fi), f1 = __builtin_nontemporal_load(fi + 1);
+            __builtin_nontemporal_store(d2v{fma(g.dt, qv[k][0], f0[0]), fma(g.dt, qv[k][1], f0[1])}, o);
+            __builtin_nontemporal_store(d2v{fma(g.dt, qv[k][2], f1[0]), fma(g.dt, qv[k][3], f1[1])}, o + 1);
+        }
+    }
+}
+
+__global__ void k_zero_counter(int* ctr) {
+    if (threadIdx.x == 0) *ctr = 0;
+}
+
 template <int N>
 int grid_for(int device) {
     int cus = 0;
@@ -528,8 +693,8 @@ int grid_for(int device) {
     int per = 0;
     constexpr int NT = N * N / Cfg<N>::P;
     int per1 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_terms<N, false>, NT, 0) != hipSuccess || per <= 0) per = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, k_terms<N, true>, NT, 0) != hipSuccess || per1 <= 0) per1 = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_terms<N, 0>, NT, 0) != hipSuccess || per <= 0) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, k_terms<N, 1>, NT, 0) != hipSuccess || per1 <= 0) per1 = 1;
     per = std::min(per, per1);
     int g = cus * per;
     return std::max(16, (g / 16) * 16);   // whole XCD pairs: multiple of 16 workgroups
@@ -639,11 +804,11 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     hipError_t e = prof_mark(0, st);
     if (e != hipSuccess) return e;
     if (one) {
-        k_terms<N, true><<<(unsigned)one_grid(p, s.ncell), NT, 0, st>>>(a);
+        k_terms<N, 1><<<(unsigned)one_grid(p, s.ncell), NT, 0, st>>>(a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         return prof_mark(1, st);
     }
-    k_terms<N, false><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
+    k_terms<N, 0><<<(unsigned)(2 * a.npairs), NT, 0, st>>>(a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = prof_mark(1, st)) != hipSuccess) return e;
     k_finish<N><<<(unsigned)s.ncell, finish_threads<N>(), 0, st>>>(a);
@@ -651,7 +816,200 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     return prof_mark(2, st);
 }
 
+// Work-queue plan of several segments of one n: cells whose term count is much larger
+// than the average item get cut into nchunk term ranges (about four items per resident
+// workgroup, no range shorter than four terms), and segments are ordered by item length,
+// longest first.
+struct QueuePlan {
+    int nseg = 0;
+    int order[kMaxQSeg];
+    int nchunk[kMaxQSeg];
+    int64_t items = 0, slots = 0, cells = 0;
+};
+QueuePlan queue_plan(const fks_segment* const* g, int nseg) {
+    QueuePlan q;
+    q.nseg = nseg;
+    const int64_t G = g[0]->plan->fused_grid;
+    int64_t units = 0;
+    for (int i = 0; i < nseg; ++i) units += g[i]->ncell * (g[i]->plan->J + 1);
+    const int64_t len = std::max<int64_t>(4, (units + 4 * G - 1) / (4 * G));
+    for (int i = 0; i < nseg; ++i) {
+        const int J = g[i]->plan->J;
+        q.nchunk[i] = (int)std::min<int64_t>({16, J, std::max<int64_t>(1, (J + len - 1) / len)});
+        q.order[i] = i;
+        q.slots += g[i]->ncell * q.nchunk[i];
+        q.cells += g[i]->ncell;
+    }
+    q.items = q.slots;
+    auto cost = [&](int i) { return (g[i]->plan->J + q.nchunk[i] - 1) / q.nchunk[i]; };
+    std::stable_sort(q.order, q.order + nseg, [&](int a, int b) { return cost(a) > cost(b); });
+    return q;
+}
+
+template <int N>
+hipError_t launch_queue(const fks_segment* const* g, int nseg, void* ws, hipStream_t st) {
+    constexpr int NT = N * N / Cfg<N>::P;
+    constexpr size_t HS = (size_t)(N / 2) * N * N;
+    const QueuePlan qp = queue_plan(g, nseg);
+    const fks_plan* p0 = g[0]->plan;
+    char* base = (char*)ws;
+    QueueArgs a{};
+    a.fh = reinterpret_cast<cx<float>*>(base);
+    const size_t part_off = align256((size_t)p0->fused_grid * HS * sizeof(cx<float>));
+    a.part = reinterpret_cast<float*>(base + part_off);
+    a.ctr = reinterpret_cast<int*>(base + part_off + align256((size_t)qp.slots * N * N * N * sizeof(float)));
+    a.nseg = nseg;
+    a.nitems = qp.items;
+    a.ncell = qp.cells;
+    int64_t item = 0, cell = 0;
+    for (int k = 0; k < nseg; ++k) {
+        const int i = qp.order[k];
+        const fks_segment& s = *g[i];
+        QSeg& q = a.seg[k];
+        q.f = s.f;
+        q.f_base = s.f_base ? s.f_base : s.f;
+        q.q_out = s.q_out;
+        q.f_out = s.f_out;
+        q.tab = reinterpret_cast<const cx<float>*>(s.plan->d_tab32);
+        q.gc = s.plan->d_gc;
+        q.guard = s.plan->d_guard;
+        q.dt = s.dt_over_tau;
+        q.item0 = item;
+        q.part0 = item;   // one partial slot per item, in item order
+        q.cell0 = cell;
+        q.J = s.plan->J;
+        q.nchunk = qp.nchunk[i];
+        item += s.ncell * q.nchunk;
+        cell += s.ncell;
+    }
+    k_zero_counter<<<1, 64, 0, st>>>(a.ctr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = prof_mark(0, st);
+    if (e != hipSuccess) return e;
+    const int64_t grid = std::min<int64_t>(p0->fused_grid, qp.items);
+    k_terms<N, 2><<<(unsigned)grid, NT, 0, st>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = prof_mark(1, st)) != hipSuccess) return e;
+    k_finish_q<N><<<(unsigned)qp.cells, finish_threads<N>(), 0, st>>>(a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return prof_mark(2, st);
+}
+
 }  // namespace
+
+namespace {
+// n = 48: the forward transform (multi-pass, into the half spectrum), the on-chip terms
+// kernel with three workgroups per cell, then the FP64 fix and update, per chunk of at most
+// kChunk48 cells.  Workspace per chunk: the complex n^3 work array of the forward passes,
+// reused as the FP32 accumulator once the spectrum is built; the half spectrum; the
+// workgroups' item counters.
+constexpr int64_t kChunk48 = 512;
+struct Ws48 {
+    int64_t chunk;
+    size_t fh, ctr, total;
+};
+inline Ws48 ws48(int64_t ncell) {
+    constexpr size_t N3 = 48 * 48 * 48, H = 25 * 48 * 48;
+    Ws48 w{};
+    w.chunk = std::min<int64_t>(std::max<int64_t>(ncell, 1), kChunk48);
+    w.fh = align256((size_t)w.chunk * N3 * sizeof(cx<float>));
+    w.ctr = w.fh + align256((size_t)w.chunk * H * sizeof(cx<float>));
+    w.total = w.ctr + 256;
+    return w;
+}
+
+// Segments of n = 48 in one call: cells are taken in chunks of at most kChunk48, segments
+// ordered by term count (longest first, so that the per-XCD queues end evenly); a chunk is
+// a list of pieces (a segment's cell range).  Per chunk: the forward transform of every
+// piece, one terms launch over all pieces, the fix and update of every piece.
+hipError_t launch48(const fks_segment* const* g, int nseg, void* ws, hipStream_t st) {
+    constexpr int64_t N3 = 48 * 48 * 48, H = 25 * 48 * 48;
+    int64_t total = 0;
+    for (int i = 0; i < nseg; ++i) total += g[i]->ncell;
+    const Ws48 w = ws48(total);
+    char* base = (char*)ws;
+    cx<float>* work = reinterpret_cast<cx<float>*>(base);
+    float* acc = reinterpret_cast<float*>(base);   // the work array once the spectrum is built
+    cx<float>* fh = reinterpret_cast<cx<float>*>(base + w.fh);
+    int* ctr = reinterpret_cast<int*>(base + w.ctr);
+    std::vector<int> order(nseg);
+    for (int i = 0; i < nseg; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g[a]->plan->J > g[b]->plan->J; });
+    struct Run {
+        const fks_segment* s;
+        int64_t c0, count;
+    };
+    int k = 0;
+    int64_t next = 0;   // next cell of segment order[k]
+    while (k < nseg) {
+        std::vector<Run> runs;
+        int64_t C = 0;
+        while (k < nseg && C < w.chunk && (int)runs.size() < kMaxPieces48) {
+            const fks_segment* s = g[order[k]];
+            const int64_t take = std::min(s->ncell - next, w.chunk - C);
+            runs.push_back(Run{s, next, take});
+            C += take;
+            next += take;
+            if (next == s->ncell) {
+                ++k;
+                next = 0;
+            }
+        }
+        Piece48 pc[kMaxPieces48];
+        int64_t off = 0;
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < runs.size() && e == hipSuccess; ++i) {
+            const Run& r = runs[i];
+            pc[i] = Piece48{reinterpret_cast<const cx<float>*>(r.s->plan->d_tab32), off, r.s->plan->J};
+            e = forward_f32_48(r.s->f + r.c0 * N3, work + off * N3, fh + off * H, (int)r.count, st);
+            off += r.count;
+        }
+        if (e == hipSuccess) e = prof_mark(0, st);
+        if (e == hipSuccess) e = terms48(fh, pc, (int)runs.size(), acc, C, ctr, g[0]->plan->fused_grid, st);
+        if (e == hipSuccess) e = prof_mark(1, st);
+        Fin48 fin[kMaxPieces48];
+        off = 0;
+        for (size_t i = 0; i < runs.size(); ++i) {
+            const Run& r = runs[i];
+            const fks_segment& s = *r.s;
+            fin[i] = Fin48{s.f_base ? s.f_base : s.f, s.q_out, s.f_out, s.plan->d_gc, s.plan->d_guard,
+                           s.dt_over_tau, off, r.c0};
+            off += r.count;
+        }
+        if (e == hipSuccess) e = finish48(acc, fin, (int)runs.size(), C, st);
+        if (e == hipSuccess) e = prof_mark(2, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace
+
+int fused_queue_max_segments() { return kMaxQSeg; }
+
+size_t fused_queue_workspace_bytes(const fks_segment* const* g, int nseg) {
+    const int n = g[0]->plan->desc.n;
+    if (n == 48) {
+        int64_t total = 0;
+        for (int i = 0; i < nseg; ++i) total += g[i]->ncell;
+        return ws48(total).total;
+    }
+    const QueuePlan qp = queue_plan(g, nseg);
+    const size_t HS = (size_t)(n / 2) * n * n;
+    return align256((size_t)g[0]->plan->fused_grid * HS * sizeof(cx<float>)) +
+           align256((size_t)qp.slots * n * n * n * sizeof(float)) + 256;
+}
+
+hipError_t collide_fused_queue(const fks_segment* const* g, int nseg, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (nseg < 1 || nseg > kMaxQSeg || ws_bytes < fused_queue_workspace_bytes(g, nseg)) return hipErrorInvalidValue;
+    switch (g[0]->plan->desc.n) {
+        case 48: return launch48(g, nseg, ws, st);
+        case 8: return launch_queue<8>(g, nseg, ws, st);
+        case 16: return launch_queue<16>(g, nseg, ws, st);
+        case 24: return launch_queue<24>(g, nseg, ws, st);
+        case 32: return launch_queue<32>(g, nseg, ws, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 void profile_enable(bool on) {
     g_prof.on = on;
@@ -674,7 +1032,7 @@ hipError_t profile_last(double* ms, int cap, int* count) {
     return hipSuccess;
 }
 
-bool fused_available(int n) { return n == 8 || n == 16 || n == 24 || n == 32; }
+bool fused_available(int n) { return n == 8 || n == 16 || n == 24 || n == 32 || n == 48; }
 
 int fused_grid_size(int n, int device) {
     switch (n) {
@@ -682,15 +1040,23 @@ int fused_grid_size(int n, int device) {
         case 16: return grid_for<16>(device);
         case 24: return grid_for<24>(device);
         case 32: return grid_for<32>(device);
+        case 48: return terms48_grid(device);
         default: return 0;
     }
 }
 
-size_t fused_workspace_bytes(const fks_plan* p, int64_t ncell) { return ws_layout(p, ncell).total; }
+
+size_t fused_workspace_bytes(const fks_plan* p, int64_t ncell) {
+    return p->desc.n == 48 ? ws48(ncell).total : ws_layout(p, ncell).total;
+}
 
 hipError_t collide_fused(const fks_plan* p, const fks_segment& s, void* ws, size_t ws_bytes, hipStream_t st) {
     if (ws_bytes < fused_workspace_bytes(p, s.ncell)) return hipErrorInvalidValue;
     switch (p->desc.n) {
+        case 48: {
+            const fks_segment* one = &s;
+            return launch48(&one, 1, ws, st);
+        }
         case 8: return launch<8>(p, s, ws, st);
         case 16: return launch<16>(p, s, ws, st);
         case 24: return launch<24>(p, s, ws, st);

@@ -712,6 +712,15 @@ size_t generic_workspace_bytes(const fks_plan* p, int64_t ncell) {
            align256(chunk * NN * sizeof(float));
 }
 
+hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C, hipStream_t st) {
+    const int bs = 128;
+    const unsigned grid = (unsigned)((C * 48 * 48 + bs - 1) / bs);
+    g_fwd_x<float, 48><<<grid, bs, 0, st>>>(f, work, C);
+    g_pass_y<float, 48, -1><<<grid, bs, 0, st>>>(work, C);
+    g_fwd_z<float, 48><<<grid, bs, 0, st>>>(work, fh, C);
+    return hipGetLastError();
+}
+
 size_t spectrum_workspace_bytes(int n, int64_t ncell) {
     const size_t chunk = (size_t)std::min<int64_t>(std::max<int64_t>(ncell, 1), kChunk);
     return chunk * (size_t)n * n * n * sizeof(cx<double>);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/fks.h"
+#include "fks_fft.hpp"
 
 namespace fks {
 
@@ -90,6 +91,36 @@ bool generic_multi_terms(const fks_plan* plan);   // several terms per launch av
 hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
                            hipStream_t stream);
 
+// n = 48 FP32 forward transform for the on-chip terms kernel (fks_generic.hip): f into the
+// half spectrum [C][n/2+1][n][n] (work: [C][n^3] complex)
+hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C, hipStream_t st);
+
+// n = 48 FP32 terms, three workgroups per cell (fks_fused48.hip): resident grid, and the
+// launch over consecutive cell ranges (pieces) that each share a plan's tables (item
+// counters [8] in device memory, cleared by the call)
+constexpr int kMaxPieces48 = 16;
+struct Piece48 {
+    const cx<float>* tab;   // [J][n/2+1][n][n] balanced FP32 tables
+    int64_t cell0;          // first cell of the piece in the launch's cell order
+    int J;
+};
+// FP64 fix and update after the terms kernel, all pieces of a chunk in one launch: the
+// piece's outputs are indexed by c0 + (cell - cell0)
+struct Fin48 {
+    const double* f_base;
+    double* q_out;
+    double* f_out;
+    const GridConst* gc;
+    unsigned long long* guard;
+    double dt;
+    int64_t cell0;          // first cell of the piece in the chunk
+    int64_t c0;             // its first cell within its segment
+};
+hipError_t finish48(const float* acc, const Fin48* pieces, int npieces, int64_t ncell, hipStream_t st);
+int terms48_grid(int device);
+hipError_t terms48(const cx<float>* fh, const Piece48* pieces, int npieces, float* acc, int64_t ncell, int* ctr,
+                   int grid, hipStream_t st);
+
 // spectrum of a batch (multi-pass FP64, fks_generic.hip)
 size_t spectrum_workspace_bytes(int n, int64_t ncell);
 hipError_t spectrum(const double* x, double* xhat, int64_t ncell, int n, int zero_nyquist, void* ws, size_t ws_bytes,
@@ -105,6 +136,13 @@ int fused_grid_size(int n, int device);
 size_t fused_workspace_bytes(const fks_plan* plan, int64_t ncell);
 hipError_t collide_fused(const fks_plan* plan, const fks_segment& seg, void* ws, size_t ws_bytes,
                          hipStream_t stream);
+
+// several fused segments of one n in one work queue (fks_fused.hip): at most
+// fused_queue_max_segments() segments, all with ncell > 0 and the same n
+int fused_queue_max_segments();
+size_t fused_queue_workspace_bytes(const fks_segment* const* segs, int nseg);
+hipError_t collide_fused_queue(const fks_segment* const* segs, int nseg, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
 
 // two velocity dimensions (fks_2d.hip)
 bool supported_n_2d(int n, int precision);

@@ -44,7 +44,7 @@ def test_fused_choice_is_kept_and_followed():
         assert _kernels(lambda: fks.collide(plan, g, q_out=torch.empty_like(g))) == 2
 
 
-@pytest.mark.parametrize("n,prec,flags", [(48, fks.PREC_F32_FIX64, 0), (16, fks.PREC_F64, 0),
+@pytest.mark.parametrize("n,prec,flags", [(48, fks.PREC_F32_FIX64, fks.FLAG_FORCE_GENERIC), (16, fks.PREC_F64, 0),
                                           (8, fks.PREC_F32_FIX64, fks.FLAG_DEALIAS)])
 def test_multi_pass_chunking_is_bit_identical(n, prec, flags):
     ncell = 100

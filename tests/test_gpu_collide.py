@@ -173,11 +173,12 @@ def test_collide_f64_vhs_k_terms(gamma, K):
 # ---------------------------------------------------------------- FP32 + FP64 fix
 
 @pytest.mark.parametrize("n,ncell,generic", [(8, 9, False), (16, 5, False), (24, 7, False), (32, 6, False),
-                                             (8, 4, True), (12, 3, True), (24, 2, True), (32, 2, True)])
+                                             (48, 5, False), (8, 4, True), (12, 3, True), (24, 2, True),
+                                             (32, 2, True), (48, 2, True)])
 def test_collide_f32_matches_oracle(n, ncell, generic):
     flags = fks.FLAG_FORCE_GENERIC if generic else 0
     plan = _plan(n=n, T=T_BOX, precision=fks.PREC_F32_FIX64, flags=flags)
-    assert plan.info.fused == (0 if generic or n not in (8, 16, 24, 32) else 1)
+    assert plan.info.fused == (0 if generic or n not in (8, 16, 24, 32, 48) else 1)
     op = _oplan(n, T_BOX, 1.0, 8, 4, 0)
     f = synth.two_maxwellian_cells(n, T_BOX, ncell, seed_offset=200 + n)
     q, _ = _gpu_qc(plan, f)
@@ -186,7 +187,7 @@ def test_collide_f32_matches_oracle(n, ncell, generic):
     _conservation_ok(q, n, T_BOX)
 
 
-@pytest.mark.parametrize("n,ncell", [(16, 3), (24, 5)])
+@pytest.mark.parametrize("n,ncell", [(16, 3), (24, 5), (48, 2)])
 def test_collide_f32_vhs_k_terms_fused(n, ncell):
     plan = _plan(n=n, T=T_BOX, gamma=0.5, radial_terms=4, precision=fks.PREC_F32_FIX64)
     assert plan.info.fused == 1
@@ -280,6 +281,67 @@ def test_multi_segment_uneven_batch():
         _check_f32(q.cpu().numpy(), r, ratio)
 
 
+@pytest.mark.parametrize("n", [16, 24, 32])
+def test_work_queue_of_same_n_segments(n):
+    # fused segments of one n in one call share a work queue: long cells are cut into term
+    # ranges (partials, then one finish kernel over all segments); q_out, in-place f_out and a
+    # Runge-Kutta stage (f_base) in one call.  Every cell against the FP64 path of the same
+    # plan (cancellation-aware bound, loss ratios from the oracle), sampled cells against the
+    # oracle, exact conservation
+    specs = [dict(gamma=1.0, n_polar=8, n_azim=4, radial_terms=0, cells=13),
+             dict(gamma=0.5, n_polar=8, n_azim=4, radial_terms=5, cells=6),
+             dict(gamma=1.0, n_polar=4, n_azim=4, radial_terms=0, cells=21),
+             dict(gamma=0.0, n_polar=8, n_azim=8, radial_terms=3, cells=4)]
+    dt = 0.02
+    segs, keep = [], []
+    for i, sp in enumerate(specs):
+        kw = dict(n=n, T=T_BOX, gamma=sp["gamma"], n_polar=sp["n_polar"], n_azim=sp["n_azim"],
+                  radial_terms=sp["radial_terms"])
+        p32, p64 = _plan(**kw, precision=fks.PREC_F32_FIX64), _plan(**kw, precision=fks.PREC_F64)
+        c = sp["cells"]
+        f = synth.two_maxwellian_torch(n, T_BOX, c, "cuda", seed_offset=400 + 10 * n + i)
+        q64 = torch.empty_like(f)
+        fks.collide(p64, f, q_out=q64)
+        if i == 0:
+            q = torch.empty_like(f)
+            segs.append((p32, f, q, None, c, 0.0))
+            keep.append((f, q64, q, None, kw))
+        elif i == 1:      # in place
+            g = f.clone()
+            segs.append((p32, g, None, g, c, dt))
+            keep.append((f, q64, None, g, kw))
+        else:             # stage: f_out = f_base + dt Q(f)
+            base = f * 0.5
+            g = torch.empty_like(f)
+            qq = torch.empty_like(f)
+            segs.append((p32, f, qq, g, c, dt, base))
+            keep.append((f, q64, qq, (g, base), kw))
+    fks.profile_enable(True)
+    try:
+        fks.collide_batch(segs)
+        assert len(fks.profile_last()) == 2          # one queue: terms, then finish
+    finally:
+        fks.profile_enable(False)
+    torch.cuda.synchronize()
+    for i, (f, q64, q, out, kw) in enumerate(keep):
+        if q is None:                                 # in place: recover Q from f_out
+            q = (out - f) / dt
+        op = _oplan(n, T_BOX, kw["gamma"], kw["n_polar"], kw["n_azim"], kw["radial_terms"])
+        ratio = _loss_ratios(f.cpu().numpy(), q64.cpu().numpy(), op)
+        err = torch.sqrt(torch.sum((q - q64) ** 2, dim=(1, 2, 3)) / torch.sum(q64 ** 2, dim=(1, 2, 3))).cpu().numpy()
+        # in place the FP64 sum f + dt Q rounds Q at the scale of f: allow that rounding
+        slack = 0.0 if i != 1 else 4e-16 * float(torch.max(torch.abs(f))) / dt / float(torch.max(torch.abs(q64)))
+        assert np.all(err <= 1.5e-6 * (1.0 + ratio) + slack), (i, err.max(), ratio[err.argmax()])
+        assert _conservation_torch(q64, n, T_BOX) <= 1e-12
+        if i >= 2:
+            g, base = out
+            assert float(torch.max(torch.abs(g - (base + dt * q)))) <= 1e-15 * float(torch.max(torch.abs(base)))
+            assert _conservation_torch(q, n, T_BOX) <= 1e-12
+        ref, rr = _oracle_qc(f[:1].cpu().numpy(), op, ratios=True)
+        e = _rel(q[0].cpu().numpy(), ref[0])       # one cell: its own cancellation-aware bound
+        assert e <= 1.5e-6 * (1.0 + rr[0]), (i, e, rr[0])
+
+
 # ---------------------------------------------------------------- the two fused decompositions
 
 def _kernels_of_last_call(call):
@@ -348,6 +410,37 @@ def test_one_workgroup_per_cell_matches_pairs_fp64_and_oracle(n):
     assert torch.equal(q2, q)
     assert float(torch.max(torch.abs(g2 - (f + dt * q)))) <= 1e-15 * float(torch.max(torch.abs(f)))
     # update in place (f_out aliases f) through the one-workgroup kernel
+    g = f.clone()
+    fks.collide(plan, g, f_out=g, dt_over_tau=dt)
+    torch.cuda.synchronize()
+    assert float(torch.max(torch.abs(g - (f + dt * q)))) <= 1e-15 * float(torch.max(torch.abs(f)))
+
+
+def test_n48_three_workgroups_per_cell_large_batch():
+    # n = 48: three workgroups per cell (one per residue of x mod 3) fed from per-XCD item
+    # counters, over two chunks of cells (512 + 89); every cell against the FP64 path to the
+    # cancellation-aware bound, sampled cells against the oracle, in-place update
+    n, ncell = 48, 601
+    plan = _plan(n=n, T=T_BOX, precision=fks.PREC_F32_FIX64)
+    assert plan.info.fused == 1 and plan.info.fused_grid >= 8
+    f = synth.two_maxwellian_torch(n, T_BOX, ncell, "cuda", seed_offset=290)
+    q = torch.empty_like(f)
+    fks.collide(plan, f, q_out=q)
+    p64 = _plan(n=n, T=T_BOX, precision=fks.PREC_F64)
+    q64 = torch.empty_like(f)
+    fks.collide(p64, f, q_out=q64)
+    torch.cuda.synchronize()
+    err = torch.sqrt(torch.sum((q - q64) ** 2, dim=(1, 2, 3)) / torch.sum(q64 ** 2, dim=(1, 2, 3)))
+    agg = float(torch.sqrt(torch.sum((q - q64) ** 2) / torch.sum(q64 ** 2)))
+    assert agg <= 1e-5, agg
+    ratio_all = _loss_ratios(f.cpu().numpy(), q64.cpu().numpy(), _oplan(n, T_BOX, 1.0, 8, 4, 0))
+    bad = np.nonzero(err.cpu().numpy() > 1.5e-6 * (1.0 + ratio_all))[0]
+    assert bad.size == 0, [(int(c), float(err[c]), float(ratio_all[c])) for c in bad[:5]]
+    assert _conservation_torch(q, n, T_BOX) <= 1e-12
+    sample = [0, 7, 511, 512, ncell - 1]
+    ref, ratio = _oracle_qc(f[sample].cpu().numpy(), _oplan(n, T_BOX, 1.0, 8, 4, 0), ratios=True)
+    _check_f32(q[sample].cpu().numpy(), ref, ratio)
+    dt = 0.01
     g = f.clone()
     fks.collide(plan, g, f_out=g, dt_over_tau=dt)
     torch.cuda.synchronize()

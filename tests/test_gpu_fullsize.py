@@ -3,8 +3,8 @@ oracle evaluates one by one and through properties that hold at any size:
 
   * uneven batch: 2048 cells, (n, M, gamma) drawn from {16, 24, 32, 48} x
     {16, 32, 64} x {0, 0.5, 1}, two-Maxwellian data, one fks_collide_batch call
-    over 36 segments, FP32 + FP64 fix (fused kernels at n <= 32, the
-    multi-pass path at n = 48) and the plain FP64 path;
+    over 36 segments, FP32 + FP64 fix (fused kernels; three workgroups per
+    cell at n = 48) and the plain FP64 path;
   * 3D x 3D periodic blast: 32^3 cells x 24^3 velocities, VHS gamma = 0.5
     with K = 7 radial terms (225 terms per cell), tau = 0.3.
 """
@@ -75,7 +75,7 @@ def test_uneven_batch_full_size():
     for (n, M, gamma), (f, q, q64, plan, gi) in data.items():
         assert _conservation(q, n, T) <= 1e-12, (n, M, gamma)
         assert _conservation(q64, n, T) <= 1e-12, (n, M, gamma)
-        assert plan.info.fused == (1 if n <= 32 else 0)
+        assert plan.info.fused == 1
         agg = float(torch.sqrt(torch.sum((q - q64) ** 2) / torch.sum(q64 ** 2)))
         assert agg <= 1e-5, ((n, M, gamma), agg)
     # sampled cells against the oracle: one per (n, gamma), from the cheapest M (n = 48 with
