@@ -541,50 +541,70 @@ def main():
         groups = {}
         for c in range(2048):
             groups.setdefault((int(ns[c]), int(Ms[c]), float(gs[c])), []).append(c)
-        segs, plans_u, pts, flops = [], [], 0, 0.0
+        segs, segs64, plans_u, pts, flops = [], [], [], 0, 0.0
         for gi, (key, cells) in enumerate(sorted(groups.items())):
             nu_, mu_, gu_ = key
             npol, naz = synth.UNEVEN_SPLIT[mu_]
             pu = fks.Plan(fks.Desc(n=nu_, T=T_BOX, gamma=gu_, n_polar=npol, n_azim=naz,
                                    precision=fks.PREC_F32_FIX64))
-            plans_u.append(pu)
+            pu64 = fks.Plan(fks.Desc(n=nu_, T=T_BOX, gamma=gu_, n_polar=npol, n_azim=naz,
+                                     precision=fks.PREC_F64))
+            plans_u += [pu, pu64]
             fu = synth.two_maxwellian_torch(nu_, T_BOX, len(cells), dev, seed_offset=500 + gi)
-            segs.append((pu, fu, None, torch.empty_like(fu), len(cells), DT_OVER_TAU))
+            out = torch.empty_like(fu)
+            segs.append((pu, fu, None, out, len(cells), DT_OVER_TAU))
+            segs64.append((pu64, fu, None, out, len(cells), DT_OVER_TAU))
             pts += len(cells) * nu_ ** 3
             flops += len(cells) * pu.info.flops_per_cell
 
-        def time_uneven(reps=2):
-            wsu = torch.empty(max(fks.workspace_size(segs), 1), dtype=torch.uint8, device=dev)
-            fks.collide_batch(segs, workspace=wsu)
+        def time_uneven(sg, reps=3):
+            # the whole call captured once as a graph, then replayed
+            wsu = torch.empty(max(fks.workspace_size(sg), 1), dtype=torch.uint8, device=dev)
+            fks.collide_batch(sg, workspace=wsu)
+            torch.cuda.synchronize()
+            capu = torch.cuda.Stream()
+            capu.wait_stream(stream)
+            gu = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gu, stream=capu):
+                fks.collide_batch(sg, workspace=wsu)
+            torch.cuda.synchronize()
+            gu.replay()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(reps):
-                fks.collide_batch(segs, workspace=wsu)
+                gu.replay()
             e1.record(stream)
             torch.cuda.synchronize()
+            del gu, wsu
             return e0.elapsed_time(e1) / reps
 
-        ms_cost = time_uneven()
+        ms_cost = time_uneven(segs)
         choices = fks.autotune(segs)
-        ms_tuned = time_uneven()
+        ms_tuned = time_uneven(segs)
+        ms_u64 = time_uneven(segs64, reps=1)
         uneven_line = {"workload": "2048 cells, (n, M, gamma) from {16,24,32,48} x {16,32,64} x {0,0.5,1}, "
                                    "36 segments in one call, FP32 + FP64 fix, f_out",
+                       "timing": "hipGraph replay of the whole call",
                        "ms_cost_model": round(ms_cost, 3), "ms_autotuned": round(ms_tuned, 3),
+                       "ms_fp64_path": round(ms_u64, 3),
+                       "speedup_fp32fix_over_fp64": round(ms_u64 / ms_tuned, 2),
                        "value": pts / (ms_tuned * 1e-3), "unit": UNIT,
                        "algorithmic_tflops": round(flops / (ms_tuned * 1e-3) / 1e12, 2),
                        "roofline": {"bound": "alu", "achieved": round(flops / (ms_tuned * 1e-3) / 1e12, 2),
                                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                     "frac": round(flops / (ms_tuned * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)},
-                       "schedules": {"fused_one_per_cell": sum(1 for o, c, t in choices if o == 1),
-                                     "fused_pairs": sum(1 for o, c, t in choices if o == 0),
-                                     "multi_pass_chunks": sorted({c for o, c, t in choices if c > 0}),
-                                     "multi_pass_terms_per_launch": sorted({t for o, c, t in choices if t > 0})}}
+                       "launch_groups": "one work queue per n in {16, 24, 32} over its 9 segments (term "
+                                        "ranges, partials, one FP64 finish); n = 48: one launch of the "
+                                        "three-workgroup kernel over its 9 segments; the FP64 leg runs "
+                                        "segment by segment on the multi-pass path",
+                       "autotuned_alone": {"fused_one_per_cell": sum(1 for o, c, t in choices if o == 1),
+                                           "fused_pairs": sum(1 for o, c, t in choices if o == 0)}}
         for pu in plans_u:
             pu.close()
-        del segs
-        print(f"[bench] uneven: {ms_cost:.2f} ms (cost model), {ms_tuned:.2f} ms (autotuned)",
-              file=sys.stderr, flush=True)
+        del segs, segs64
+        print(f"[bench] uneven: {ms_cost:.2f} ms (cost model), {ms_tuned:.2f} ms (autotuned), "
+              f"FP64 path {ms_u64:.2f} ms", file=sys.stderr, flush=True)
 
     # plain FP64 path (multi-pass), same workload
     fp64 = None

@@ -10,7 +10,9 @@
 // their z and y inverse transforms (48 points) and 16-point transforms over k1.  A
 // workgroup owns one (cell, r): it reads the whole half spectrum of the term (tables
 // and fhat, from L2), keeps its 16 x 48 x 48 slice on chip and adds Re z Im z to its
-// third of Q+ (FP32, in the workspace: the registers hold the term's slice).  No data
+// third of Q+: two thirds of those accumulators stay in registers over the terms, the
+// last third is read and written in the workspace every term (keeping all of them in
+// registers, or none, spills more and ran slower).  No data
 // moves between workgroups; the FP64 fix runs afterwards over the whole cell.
 //
 // Thread layouts (768 threads, 12 waves):
@@ -171,10 +173,12 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
         const cx<float> w3 = c_w48.w[16 * r], w3b = c_w48.w[(32 * r) % 48];
         const Piece48 pce = piece_of(A, cell);
         const char* const fhb = reinterpret_cast<const char*>(A.fh + cell * (int64_t)H);
-        // Q+ of this third of the cell, accumulated in place over the terms (the registers
-        // hold the term's slice): node (3m + r, 16 rho + ub, uz) at byte offset
-        // 4 (3m NN + 16 rho N) + qo from the uniform base
+        // Q+ of this third of the cell: node (3m + r, 16 rho + ub, uz), at byte offset
+        // 4 (3m NN + 16 rho N) + qo from the uniform base; rounds rho = 0, 1 accumulate in
+        // registers, round 2 in place in the workspace
         char* const qb = reinterpret_cast<char*>(A.acc + cell * (int64_t)N3 + r * NN);
+        float q0[2][16];   // rounds 0 and 1
+        sfor<2>([&](auto rI) { sfor<16>([&](auto mI) { q0[decltype(rI)::value][decltype(mI)::value] = 0.0f; }); });
 
         for (int j = 0; j < pce.J; ++j) {
             const char* const tjb = reinterpret_cast<const char*>(pce.tab + (size_t)j * H);
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                 float prev[16];
                 const uint32_t qo = opaque48(uint32_t(ub * N + uz) * 4u);
                 sfor<16>([&](auto mI) { prev[decltype(mI)::value] = 0.0f; });
-                if (j > 0) {
+                if (rho > 1 && j > 0) {
                     sfor<16>([&](auto mI) {
                         constexpr int m = decltype(mI)::value;
                         constexpr uint32_t mo = (3 * m * NN + 16 * rho * N) * 4u;
@@ -269,7 +273,18 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                 sfor<16>([&](auto mI) {
                     constexpr int m = decltype(mI)::value;
                     constexpr uint32_t mo = (3 * m * NN + 16 * rho * N) * 4u;
-                    *reinterpret_cast<float*>(qb + (qo + mo)) = fmaf(xc[m].x, xc[m].y, prev[m]);
+                    if constexpr (rho < 2) q0[rho][m] = fmaf(xc[m].x, xc[m].y, q0[rho][m]);
+                    else *reinterpret_cast<float*>(qb + (qo + mo)) = fmaf(xc[m].x, xc[m].y, prev[m]);
+                });
+            });
+        }
+        {
+            const uint32_t qo = uint32_t(ub * N + uz) * 4u;
+            sfor<2>([&](auto rI) {
+                constexpr int rho = decltype(rI)::value;
+                sfor<16>([&](auto mI) {
+                    constexpr int m = decltype(mI)::value;
+                    *reinterpret_cast<float*>(qb + (qo + uint32_t(3 * m * NN + 16 * rho * N) * 4u)) = q0[rho][m];
                 });
             });
         }
