@@ -431,6 +431,23 @@ fks_status fks_bgk(const fks_bgk_desc* desc, const double* f, double* q_out, dou
                    int64_t ncell, double dt_over_tau, void* hip_stream);
 
 /*
+ * Scalars of the split scheme (host, no device needed).
+ *   fks_stable_dt: the time step bound min(dx / T, tau / mu) of one split step,
+ *     transport CFL (|v| <= T on the grid) and collision stability with
+ *     mu = 4 pi C_gamma (2R)^gamma rho_max, the loss frequency of the truncated
+ *     kernel at the largest density (Section 3.1; the paper states the bound for
+ *     T = pi).  All arguments > 0 except gamma in [0, 1]; else FKS_ERR_INVALID.
+ *   fks_exp_euler_step: the step length h = (1 - exp(-mu dt_over_tau)) / mu of the
+ *     exponential Euler collision step f + h Q_c(f) for stiff collisions (the
+ *     penalised form Q = [Q + mu (f - M)] - mu (f - M) with the linear part
+ *     integrated exactly); h -> dt_over_tau as mu dt_over_tau -> 0 and h <= 1/mu.
+ *     mu > 0 and dt_over_tau >= 0, finite; else FKS_ERR_INVALID.
+ */
+fks_status fks_stable_dt(double dx, double T, double tau, double R, double gamma, double c_gamma,
+                         double rho_max, double* dt);
+fks_status fks_exp_euler_step(double mu, double dt_over_tau, double* h);
+
+/*
  * Host-only helpers (no device needed), exposed so that the host precompute
  * can be checked without a GPU.
  *   fks_desc_validate: the validation fks_plan_create performs.

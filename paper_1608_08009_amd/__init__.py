@@ -46,6 +46,7 @@ EXPORTED = [
     "fks_host_tables_2d", "fks_bgk", "fks_spectrum_workspace_size", "fks_spectrum",
     "fks_numeric_status", "fks_autotune_workspace_size", "fks_autotune",
     "fks_halo_size", "fks_halo_pack", "fks_transport_shift_slab", "fks_collide_batch_static",
+    "fks_stable_dt", "fks_exp_euler_step",
 ]
 
 STATIC_WORKSPACE_BYTES = 64 << 20   # FKS_STATIC_WORKSPACE_BYTES
@@ -109,6 +110,8 @@ def lib() -> C.CDLL:
     L.fks_workspace_size.argtypes = [C.POINTER(Segment), i32, C.POINTER(sz)]
     L.fks_collide_batch.argtypes = [C.POINTER(Segment), i32, vp, sz, vp]
     L.fks_collide_batch_static.argtypes = [C.POINTER(Segment), i32, vp]
+    L.fks_stable_dt.argtypes = [dbl, dbl, dbl, dbl, dbl, dbl, dbl, C.POINTER(dbl)]
+    L.fks_exp_euler_step.argtypes = [dbl, dbl, C.POINTER(dbl)]
     L.fks_moments.argtypes = [vp, i64, i32, dbl, vp, vp]
     L.fks_conserve.argtypes = [vp, vp, i64, i32, dbl, vp]
     L.fks_transport_shift.argtypes = [vp, vp, C.POINTER(SpaceDesc), i32, dbl, dbl, vp, vp, vp]
@@ -345,6 +348,20 @@ def collide_batch_static(segments, stream=None) -> None:
     arr = _segments(segments)
     _check(lib().fks_collide_batch_static(arr, len(segments), C.c_void_p(_stream_ptr(stream))),
            "fks_collide_batch_static")
+
+
+def stable_dt(dx: float, T: float, tau: float, R: float, gamma: float, c_gamma: float, rho_max: float) -> float:
+    """fks_stable_dt: min(dx/T, tau/mu), mu = 4 pi C_gamma (2R)^gamma rho_max."""
+    out = C.c_double()
+    _check(lib().fks_stable_dt(dx, T, tau, R, gamma, c_gamma, rho_max, C.byref(out)), "fks_stable_dt")
+    return out.value
+
+
+def exp_euler_step(mu: float, dt_over_tau: float) -> float:
+    """fks_exp_euler_step: (1 - exp(-mu dt_over_tau)) / mu."""
+    out = C.c_double()
+    _check(lib().fks_exp_euler_step(mu, dt_over_tau, C.byref(out)), "fks_exp_euler_step")
+    return out.value
 
 
 def autotune(segments, workspace=None, stream=None):

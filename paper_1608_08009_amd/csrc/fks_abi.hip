@@ -326,6 +326,24 @@ const char* fks_status_string(fks_status s) {
 
 fks_status fks_desc_validate(const fks_plan_desc* desc) { return resolve_desc(desc, nullptr); }
 
+fks_status fks_stable_dt(double dx, double T, double tau, double R, double gamma, double c_gamma, double rho_max,
+                         double* dt) {
+    if (!dt) return FKS_ERR_INVALID;
+    for (double v : {dx, T, tau, R, c_gamma, rho_max})
+        if (!(v > 0) || !std::isfinite(v)) return FKS_ERR_INVALID;
+    if (!(gamma >= 0.0 && gamma <= 1.0)) return FKS_ERR_INVALID;
+    const double mu = 4.0 * kPi * c_gamma * std::pow(2.0 * R, gamma) * rho_max;
+    *dt = std::min(dx / T, tau / mu);
+    return FKS_OK;
+}
+
+fks_status fks_exp_euler_step(double mu, double dt_over_tau, double* h) {
+    if (!h || !(mu > 0) || !std::isfinite(mu) || !(dt_over_tau >= 0) || !std::isfinite(dt_over_tau))
+        return FKS_ERR_INVALID;
+    *h = -std::expm1(-mu * dt_over_tau) / mu;
+    return FKS_OK;
+}
+
 fks_status fks_profile_enable(int32_t enable) {
     profile_enable(enable != 0);
     return FKS_OK;

@@ -26,8 +26,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (BC_DIRICHLET, BC_PERIODIC, Plan, collide_batch, transport_shift,
+from . import (BC_DIRICHLET, BC_PERIODIC, Plan, collide_batch, exp_euler_step, transport_shift,
                workspace_size)
+from . import stable_dt as _stable_dt
 
 
 @dataclass
@@ -45,9 +46,8 @@ class Space:
 
 def stable_dt(space: Space, T: float, tau: float, R: float, gamma: float, c_gamma: float,
               rho_max: float) -> float:
-    """min(dx/T, tau/mu) with mu = 4 pi C_gamma (2R)^gamma rho_max (collision stability bound)."""
-    mu = 4.0 * math.pi * c_gamma * (2.0 * R) ** gamma * rho_max
-    return min(space.dx / T, tau / mu)
+    """min(dx/T, tau/mu) with mu = 4 pi C_gamma (2R)^gamma rho_max (fks_stable_dt)."""
+    return _stable_dt(space.dx, T, tau, R, gamma, c_gamma, rho_max)
 
 
 class SplitStepper:
@@ -84,7 +84,7 @@ class SplitStepper:
     def _collide(self, src, dst, dt_over_tau: float) -> None:
         nc = self.space.ncell
         if self.collision == "exp":
-            h = -math.expm1(-self.mu * dt_over_tau) / self.mu
+            h = exp_euler_step(self.mu, dt_over_tau)
             collide_batch([(self.plan, src, None, dst, nc, h)], workspace=self.ws)
         elif self.collision == "euler":
             collide_batch([(self.plan, src, None, dst, nc, dt_over_tau)], workspace=self.ws)

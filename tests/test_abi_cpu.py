@@ -228,3 +228,24 @@ def test_static_workspace_size_and_host_validation():
     seg = (fks.Segment * 1)()
     seg[0] = fks.Segment(None, None, None, None, 4, 0.0, None)   # no plan
     assert L.fks_collide_batch_static(seg, 1, None) == fks.FKS_ERR_INVALID
+
+
+def test_split_scheme_scalars():
+    # fks_stable_dt: transport CFL or the collision bound, whichever is smaller
+    R = 2 * 8.0 / (3 + math.sqrt(2))
+    c = 1 / (4 * math.pi)
+    mu = 4 * math.pi * c * (2 * R) ** 0.5 * 1.5
+    assert fks.stable_dt(0.01, 8.0, 0.3, R, 0.5, c, 1.5) == pytest.approx(min(0.01 / 8.0, 0.3 / mu), rel=1e-15)
+    assert fks.stable_dt(1.0, 8.0, 1e-3, R, 1.0, c, 1.0) == pytest.approx(1e-3 / (2 * R), rel=1e-15)
+    # fks_exp_euler_step: Euler for small mu dt, capped at 1/mu, monotone in dt
+    assert fks.exp_euler_step(2.0, 1e-9) == pytest.approx(1e-9, rel=1e-8)
+    assert fks.exp_euler_step(2.0, 1e3) == pytest.approx(0.5, rel=1e-15)
+    h = [fks.exp_euler_step(3.0, d) for d in (0.0, 0.1, 0.2, 0.4)]
+    assert h[0] == 0.0 and all(a < b for a, b in zip(h, h[1:])) and h[-1] < 1 / 3.0
+    assert fks.exp_euler_step(3.0, 0.1) == pytest.approx((1 - math.exp(-0.3)) / 3.0, rel=1e-14)
+    L = fks.lib()
+    out = C.c_double()
+    assert L.fks_exp_euler_step(0.0, 0.1, C.byref(out)) == fks.FKS_ERR_INVALID
+    assert L.fks_exp_euler_step(1.0, -0.1, C.byref(out)) == fks.FKS_ERR_INVALID
+    assert L.fks_stable_dt(0.1, 8.0, 1.0, R, 1.5, c, 1.0, C.byref(out)) == fks.FKS_ERR_INVALID
+    assert L.fks_stable_dt(0.1, 8.0, 1.0, R, 0.5, c, 0.0, C.byref(out)) == fks.FKS_ERR_INVALID
