@@ -437,6 +437,7 @@ static void plan_free(fks_plan* p) {
     if (p->d_guard) (void)hipFree(p->d_guard);
     if (p->d_tab64) (void)hipFree(p->d_tab64);
     if (p->d_tab32) (void)hipFree(p->d_tab32);
+    if (p->d_tab32p) (void)hipFree(p->d_tab32p);
     if (p->d_gc) (void)hipFree(p->d_gc);
     if (p->d_gc2) (void)hipFree(p->d_gc2);
     delete p;
@@ -524,6 +525,14 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
         p->table_bytes += tab_elems * sizeof(float);
         p->fused = fused_available(n) && !(d.flags & (FKS_FLAG_FORCE_GENERIC | FKS_FLAG_DEALIAS));
         if (p->fused) p->fused_grid = fused_grid_size(n, p->device);
+        if (p->fused && n <= 32) {   // the kz-pair copy read by the fused kernels at n <= 32
+            const size_t pair_elems = (size_t)p->J * (n / 2) * n * n * 2;
+            if (hipMalloc(&p->d_tab32p, pair_elems * sizeof(float)) != hipSuccess) {
+                plan_free(p);
+                return FKS_ERR_NOMEM;
+            }
+            p->table_bytes += pair_elems * sizeof(float);
+        }
     }
     hipStream_t s = (hipStream_t)hip_stream;
     if (build_tables(p, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {

@@ -138,10 +138,10 @@ struct FusedArgs {
     const double* f_base;   // state of the update (f unless a Runge-Kutta stage)
     int64_t ncell;
     double dt;
-    const cx<float>* tab;   // [J][(n/2+1) n n] balanced (a, b)
+    const cx<float>* tab;   // [J][n/4][n][n][2] balanced (a, b), kz pairs adjacent
     int J;
     int npairs;
-    cx<float>* fh;          // [ncell][n/2][n][n]
+    cx<float>* fh;          // [ncell][n/4][n][n][2] (kz pairs adjacent)
     float* part;            // [ncell][2][n^3]
     const GridConst* gc;
     unsigned long long* guard;   // numeric guard word, or null
@@ -159,7 +159,7 @@ struct QSeg {
     const double* f_base;   // state of the update
     double* q_out;
     double* f_out;
-    const cx<float>* tab;   // the plan's balanced FP32 tables
+    const cx<float>* tab;   // the plan's balanced FP32 tables, kz pairs adjacent
     const GridConst* gc;
     unsigned long long* guard;
     double dt;
@@ -174,7 +174,7 @@ struct QueueArgs {
     int nseg;
     int64_t nitems;
     int64_t ncell;          // cells of all segments
-    cx<float>* fh;          // [grid][n/2][n][n]: one spectrum slot per workgroup
+    cx<float>* fh;          // [grid][n/4][n][n][2]: one spectrum slot per workgroup
     float* part;            // [slots][n^3]
     int* ctr;               // item counter, zero at launch
 };
@@ -210,8 +210,7 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
     constexpr int N3 = N * N * N;
     constexpr int RS = N + 1;        // LDS row stride (complex)
     constexpr int BS = N * RS;       // LDS block stride
-    constexpr int H = (N / 2 + 1) * N * N;   // table stride per term
-    constexpr int HS = (N / 2) * N * N;      // spectrum slot per cell
+    constexpr int HS = (N / 2) * N * N;      // spectrum slot per cell, and table stride per term
     __shared__ cx<float> lds[HP * BS];
     __shared__ double red[ONE ? 5 * (NT / 64) : 1];
     __shared__ int64_t s_item;
@@ -310,10 +309,11 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
             fft<float, N, -1>(a);
             const int kx = kx_of<N, P>(p, hi), ky = ky_of<N, P>(p, hi, lo);
             const float s = ((kx == N / 2) || (ky == N / 2)) ? 0.0f : 1.0f / (float)N3;
-            cx<float>* o = fh + opaque(kx * N + ky);
-            sfor<N / 2>([&](auto kI) {
-                constexpr int kz = decltype(kI)::value;
-                o[kz * NN] = cx<float>{a[kz].x * s, a[kz].y * s};
+            // kz pairs (2m, 2m + 1) adjacent, so that one 16-byte access moves two planes
+            float4* o = reinterpret_cast<float4*>(fh) + opaque(kx * N + ky);
+            sfor<N / 4>([&](auto mI) {
+                constexpr int m = decltype(mI)::value;
+                o[m * NN] = float4{a[2 * m].x * s, a[2 * m].y * s, a[2 * m + 1].x * s, a[2 * m + 1].y * s};
             });
         });
         __threadfence_block();
@@ -325,38 +325,45 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
             constexpr int p = decltype(pI)::value;
             sfor<N>([&](auto xI) { q[p][decltype(xI)::value] = 0.0f; });
         });
-        // table and spectrum at the own pencil (hi, lo), kz in [0, n/2): loaded one
-        // term ahead, during the last x transform of the previous term
+        // Table and spectrum at pencil (kx, ky), kz in [0, n/2), as n/4 loads of 16 bytes
+        // (kz pairs are adjacent in both; a wave's load covers 1 KiB of consecutive
+        // memory).  Half as many load instructions as 8-byte loads of the same bytes:
+        // the issue of vector memory instructions, not their bytes, limits this loop.
+        auto load_pairs = [&](auto m0I, auto m1I, const char* tj, uint32_t o16, cx<float>* t, cx<float>* f) {
+            constexpr int M0 = decltype(m0I)::value, M1 = decltype(m1I)::value;
+            sfor<M1 - M0>([&](auto mI) {
+                constexpr int m = M0 + decltype(mI)::value;
+                constexpr uint32_t zo = m * NN * sizeof(float4);
+                const float4 a = *(const float4*)(tj + (o16 + zo));
+                const float4 c = *(const float4*)((const char*)fh + (o16 + zo));
+                t[2 * m] = {a.x, a.y};
+                t[2 * m + 1] = {a.z, a.w};
+                f[2 * m] = {c.x, c.y};
+                f[2 * m + 1] = {c.z, c.w};
+            });
+        };
+        // own pencil (hi, lo): loaded one term ahead, during the last x transform of the
+        // previous term
         cx<float> pt[N / 2], pf[N / 2];
         auto load_own = [&](int jj) {
-            const char* tj = (const char*)(tab0 + (size_t)jj * H);
-            const uint32_t oa8 = uint32_t(opaque(hi * N + lo)) * 8u;
-            sfor<N / 2>([&](auto kI) {
-                constexpr int kz = decltype(kI)::value;
-                constexpr uint32_t zo = kz * NN * sizeof(cx<float>);
-                pt[kz] = *(const cx<float>*)(tj + (oa8 + zo));
-                pf[kz] = *(const cx<float>*)((const char*)fh + (oa8 + zo));
-            });
+            load_pairs(std::integral_constant<int, 0>{}, std::integral_constant<int, N / 4>{},
+                       (const char*)(tab0 + (size_t)jj * HS), uint32_t(opaque(hi * N + lo)) * 16u, pt, pf);
         };
         load_own(min(j_begin, Jt - 1));
         for (int j = j_begin; j < j_end; ++j) {
-            const cx<float>* tj = tab0 + (size_t)j * H;
+            const cx<float>* tj = tab0 + (size_t)j * HS;
             cx<float> za[P][N];
             // Products Z = (a + i b) fhat.  Own pencil (hi, lo), kz in [0, n/2): from the
-            // prefetched pt, pf; mirror pencil (-hi, -lo): loaded here in four groups of
-            // kz, each group's loads issued one phase before its products, so that about
-            // a quarter of the loads is in flight while the previous quarter is consumed
-            // (all at once, or as the compiler orders them by itself, is slower).
-            const int ob = opaque(((N - hi) % N) * N + ((N - lo) % N));
+            // prefetched pt, pf; mirror pencil (-hi, -lo): loaded here in NG groups of kz
+            // pairs, each group's loads issued one phase before its products, so that part
+            // of the loads is in flight while the previous part is consumed (all at once, or
+            // as the compiler orders them by itself, is slower).
+            const uint32_t ob16 = uint32_t(opaque(((N - hi) % N) * N + ((N - lo) % N))) * 16u;
             cx<float> mt[N / 2], mf[N / 2];
-            constexpr int NG = 4, GS = (N / 2) / NG;
-            static_assert(GS * NG == N / 2, "mirror load groups");
-            auto load_mirror = [&](auto kI) {
-                constexpr int kz = decltype(kI)::value;
-                constexpr uint32_t zo = kz * NN * sizeof(cx<float>);
-                mt[kz] = *(const cx<float>*)((const char*)tj + (uint32_t(ob) * 8u + zo));
-                mf[kz] = *(const cx<float>*)((const char*)fh + (uint32_t(ob) * 8u + zo));
-            };
+            constexpr int NPR = N / 4;   // kz pairs
+            constexpr int NG = NPR % 4 == 0 ? 4 : NPR % 3 == 0 ? 3 : 2;
+            constexpr int GS = (N / 2) / NG;   // kz per group
+            static_assert(GS * NG == N / 2 && GS % 2 == 0, "mirror load groups");
             // pencil 0 = (hi, lo): kz from (hi, lo), -kz from the mirror (conjugated);
             // pencil 1 = (-hi, -lo): kz from the mirror, -kz from (hi, lo)
             auto own_products = [&](auto kI) {
@@ -372,7 +379,8 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
             sfor<NG + 1>([&](auto phI) {
                 constexpr int ph = decltype(phI)::value;
                 if constexpr (ph < NG)
-                    sfor<GS>([&](auto kI) { load_mirror(std::integral_constant<int, ph * GS + decltype(kI)::value>{}); });
+                    load_pairs(std::integral_constant<int, ph * GS / 2>{}, std::integral_constant<int, (ph + 1) * GS / 2>{},
+                               (const char*)tj, ob16, mt, mf);
                 if constexpr (ph == 0) sfor<N / 2>([&](auto kI) { own_products(kI); });
                 if constexpr (ph > 0)
                     sfor<GS>([&](auto kI) { mirror_products(std::integral_constant<int, (ph - 1) * GS + decltype(kI)::value>{}); });
@@ -794,7 +802,7 @@ hipError_t launch(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t
     a.f_base = s.f_base ? s.f_base : s.f;
     a.ncell = s.ncell;
     a.dt = s.dt_over_tau;
-    a.tab = reinterpret_cast<const cx<float>*>(p->d_tab32);
+    a.tab = reinterpret_cast<const cx<float>*>(p->d_tab32p);
     a.J = p->J;
     a.npairs = npairs_for(p, s.ncell);
     a.fh = reinterpret_cast<cx<float>*>(base + w.fh);
@@ -870,7 +878,7 @@ hipError_t launch_queue(const fks_segment* const* g, int nseg, void* ws, hipStre
         q.f_base = s.f_base ? s.f_base : s.f;
         q.q_out = s.q_out;
         q.f_out = s.f_out;
-        q.tab = reinterpret_cast<const cx<float>*>(s.plan->d_tab32);
+        q.tab = reinterpret_cast<const cx<float>*>(s.plan->d_tab32p);
         q.gc = s.plan->d_gc;
         q.guard = s.plan->d_guard;
         q.dt = s.dt_over_tau;

@@ -55,6 +55,8 @@ struct fks_plan {
     std::vector<double> rad_coef;   // [nq][K]
     double* d_tab64 = nullptr;      // [J][H][2] (omega*alpha, beta) FP64
     float* d_tab32 = nullptr;       // same, rounded to FP32 (FP32 plans only)
+    float* d_tab32p = nullptr;      // fused kernels at n <= 32: d_tab32's planes kz < n/2 as
+                                    // [J][n/4][n][n][2] complex (kz pairs adjacent)
     fks::GridConst* d_gc = nullptr; // device copy of gc
     int dim = 3;                    // velocity dimension
     unsigned long long* d_guard = nullptr;   // first non-finite cell (numeric guard), ~0 = none

@@ -101,6 +101,21 @@ __global__ void k_round(const double* __restrict__ tab64, float* __restrict__ ta
     tab32[o + 1] = (float)(tab64[o + 1] / s);
 }
 
+// The FP32 table's planes kz < n/2 regrouped for the fused kernels: complex element
+// (j, kz, kx, ky) goes to ((j (n/4) + kz/2) n^2 + kx n + ky) 2 + kz % 2, so that the two
+// planes of a kz pair sit side by side and one 16-byte load reads both.
+__global__ void k_pairs(const float2* __restrict__ tab32, float2* __restrict__ tab32p, int J, int n, int H) {
+    const long long nn = (long long)n * n;
+    const long long per_term = (long long)(n / 2) * nn;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)J * per_term) return;
+    const int j = (int)(t / per_term);
+    const long long r = t - j * per_term;           // r = (m nn + kxy) 2 + s
+    const int s = (int)(r & 1);
+    const long long m = (r >> 1) / nn, kxy = (r >> 1) - m * nn;
+    tab32p[t] = tab32[(long long)j * H + (2 * m + s) * nn + kxy];
+}
+
 }  // namespace
 
 hipError_t build_tables(fks_plan* p, hipStream_t stream) {
@@ -148,6 +163,14 @@ hipError_t build_tables(fks_plan* p, hipStream_t stream) {
             int bs = 256;
             k_round<<<(unsigned)((total + bs - 1) / bs), bs, 0, stream>>>(p->d_tab64, p->d_tab32, d_scale, p->J,
                                                                           p->H);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && p->d_tab32p) {
+            const int n = p->desc.n;
+            long long total = (long long)p->J * (n / 2) * n * n;
+            int bs = 256;
+            k_pairs<<<(unsigned)((total + bs - 1) / bs), bs, 0, stream>>>(
+                reinterpret_cast<const float2*>(p->d_tab32), reinterpret_cast<float2*>(p->d_tab32p), p->J, n, p->H);
             e = hipGetLastError();
         }
     }
