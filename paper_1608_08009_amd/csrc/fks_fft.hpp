@@ -179,6 +179,51 @@ FKS_HD void butterfly(cx<T>* u) {
     }
 }
 
+// one output group k of a radix-R combination: y[k + M q], q < R, from sub[r][k]
+template <typename T, int N, int SIGN, int R, int M, int k>
+FKS_HD void combine(const cx<T> (&sub)[R][M], cx<T>* y) {
+    if constexpr (R == 4 && !(ScaledTwiddle<T, SIGN, N, k>::trivial &&
+                              ScaledTwiddle<T, SIGN, N, 2 * k>::trivial &&
+                              ScaledTwiddle<T, SIGN, N, 3 * k>::trivial)) {
+        using W1 = ScaledTwiddle<T, SIGN, N, k>;
+        using W2 = ScaledTwiddle<T, SIGN, N, 2 * k>;
+        using W3 = ScaledTwiddle<T, SIGN, N, 3 * k>;
+        const cx<T> u0 = sub[0][k];
+        const cx<T> v1 = W1::pre(sub[1][k]), v2 = W2::pre(sub[2][k]), v3 = W3::pre(sub[3][k]);
+        constexpr T g1 = W1::g, g2 = W2::g, g3 = W3::g;
+        const cx<T> a = {u0.x + g2 * v2.x, u0.y + g2 * v2.y};
+        const cx<T> b = {u0.x - g2 * v2.x, u0.y - g2 * v2.y};
+        cx<T> c, d;
+        if constexpr (g1 == g3) {         // c = g (v1 + v3), d = g (v1 - v3)
+            const cx<T> sp = cadd(v1, v3), sm = csub(v1, v3);
+            const cx<T> dm = cmul_i<T, SIGN>(sm);
+            y[k] = {a.x + g1 * sp.x, a.y + g1 * sp.y};
+            y[k + 2 * M] = {a.x - g1 * sp.x, a.y - g1 * sp.y};
+            y[k + M] = {b.x + g1 * dm.x, b.y + g1 * dm.y};
+            y[k + 3 * M] = {b.x - g1 * dm.x, b.y - g1 * dm.y};
+        } else {
+            const cx<T> t3 = {g3 * v3.x, g3 * v3.y};
+            c = {g1 * v1.x + t3.x, g1 * v1.y + t3.y};
+            d = cmul_i<T, SIGN>(cx<T>{g1 * v1.x - t3.x, g1 * v1.y - t3.y});
+            y[k] = cadd(a, c);
+            y[k + 2 * M] = csub(a, c);
+            y[k + M] = cadd(b, d);
+            y[k + 3 * M] = csub(b, d);
+        }
+    } else {
+        cx<T> u[R];
+        sfor<R>([&](auto rI) {
+            constexpr int r = decltype(rI)::value;
+            u[r] = twiddle<T, SIGN, N, r * k>(sub[r][k]);
+        });
+        butterfly<T, R, SIGN>(u);
+        sfor<R>([&](auto qI) {
+            constexpr int q = decltype(qI)::value;
+            y[k + M * q] = u[q];
+        });
+    }
+}
+
 // y[k] = sum_{m<N} x[OFF + IS*m] exp(SIGN 2 pi i m k / N), k = 0..N-1
 template <typename T, int N, int SIGN, int IS, int OFF, int LEN>
 FKS_HD void fft_rec(const cx<T> (&x)[LEN], cx<T>* y) {
@@ -193,49 +238,48 @@ FKS_HD void fft_rec(const cx<T> (&x)[LEN], cx<T>* y) {
             fft_rec<T, M, SIGN, IS * R, OFF + IS * r, LEN>(x, sub[r]);
         });
         sfor<M>([&](auto kI) {
-            constexpr int k = decltype(kI)::value;
-            if constexpr (R == 4 && !(ScaledTwiddle<T, SIGN, N, k>::trivial &&
-                                      ScaledTwiddle<T, SIGN, N, 2 * k>::trivial &&
-                                      ScaledTwiddle<T, SIGN, N, 3 * k>::trivial)) {
-                using W1 = ScaledTwiddle<T, SIGN, N, k>;
-                using W2 = ScaledTwiddle<T, SIGN, N, 2 * k>;
-                using W3 = ScaledTwiddle<T, SIGN, N, 3 * k>;
-                const cx<T> u0 = sub[0][k];
-                const cx<T> v1 = W1::pre(sub[1][k]), v2 = W2::pre(sub[2][k]), v3 = W3::pre(sub[3][k]);
-                constexpr T g1 = W1::g, g2 = W2::g, g3 = W3::g;
-                const cx<T> a = {u0.x + g2 * v2.x, u0.y + g2 * v2.y};
-                const cx<T> b = {u0.x - g2 * v2.x, u0.y - g2 * v2.y};
-                cx<T> c, d;
-                if constexpr (g1 == g3) {         // c = g (v1 + v3), d = g (v1 - v3)
-                    const cx<T> sp = cadd(v1, v3), sm = csub(v1, v3);
-                    const cx<T> dm = cmul_i<T, SIGN>(sm);
-                    y[k] = {a.x + g1 * sp.x, a.y + g1 * sp.y};
-                    y[k + 2 * M] = {a.x - g1 * sp.x, a.y - g1 * sp.y};
-                    y[k + M] = {b.x + g1 * dm.x, b.y + g1 * dm.y};
-                    y[k + 3 * M] = {b.x - g1 * dm.x, b.y - g1 * dm.y};
-                } else {
-                    const cx<T> t3 = {g3 * v3.x, g3 * v3.y};
-                    c = {g1 * v1.x + t3.x, g1 * v1.y + t3.y};
-                    d = cmul_i<T, SIGN>(cx<T>{g1 * v1.x - t3.x, g1 * v1.y - t3.y});
-                    y[k] = cadd(a, c);
-                    y[k + 2 * M] = csub(a, c);
-                    y[k + M] = cadd(b, d);
-                    y[k + 3 * M] = csub(b, d);
-                }
-            } else {
-                cx<T> u[R];
-                sfor<R>([&](auto rI) {
-                    constexpr int r = decltype(rI)::value;
-                    u[r] = twiddle<T, SIGN, N, r * k>(sub[r][k]);
-                });
-                butterfly<T, R, SIGN>(u);
-                sfor<R>([&](auto qI) {
-                    constexpr int q = decltype(qI)::value;
-                    y[k + M * q] = u[q];
-                });
-            }
+            combine<T, N, SIGN, R, M, decltype(kI)::value>(sub, y);
         });
     }
+}
+
+// an empty asm that takes every value of v: the values exist at this point of the
+// program, in registers, and the compiler does not move the code that computes
+// them past the memory operations that follow
+template <int K, typename T, int M>
+FKS_HD void pin_from(cx<T> (&v)[M]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (K < M) {
+        asm volatile("" : "+v"(v[K].x), "+v"(v[K].y) : : "memory");
+        pin_from<K + 1>(v);
+    }
+#endif
+}
+
+// fft (below) with a hook: hook(I) runs after first-level sub-transform I (I < R) and
+// after output group I - R of the last combination (R <= I < R + N/R), so that a
+// caller can place independent work (LDS traffic, loads) between the transform's parts
+template <typename T, int N, int SIGN, typename Hook>
+FKS_HD void fft_hook(cx<T> (&x)[N], Hook&& hook) {
+    constexpr int R = first_radix<N>();
+    constexpr int M = N / R;
+    cx<T> sub[R][M];
+    sfor<R>([&](auto rI) {
+        constexpr int r = decltype(rI)::value;
+        fft_rec<T, M, SIGN, R, r, N>(x, sub[r]);
+        pin_from<0>(sub[r]);   // the sub-transform is finished here, not sunk past the hook's work
+        hook(rI);
+    });
+    cx<T> y[N];
+    sfor<M>([&](auto kI) {
+        constexpr int k = decltype(kI)::value;
+        combine<T, N, SIGN, R, M, k>(sub, y);
+        hook(std::integral_constant<int, R + k>{});
+    });
+    sfor<N>([&](auto kI) {
+        constexpr int k = decltype(kI)::value;
+        x[k] = y[k];
+    });
 }
 
 template <typename T, int N, int SIGN>

@@ -47,7 +47,15 @@
 // VGPRs and spill the accumulators every term.  The own-pencil table and
 // spectrum values of term j+1 are loaded during the last x transform of term j
 // (software pipelining); the mirror-pencil values are loaded at the start of
-// the term.
+// the term.  Tables and spectrum slots keep the planes kz = 2m and 2m + 1 side
+// by side, so that each of these loads moves 16 bytes: the number of vector
+// memory instructions, not their bytes, bounds the term loop (8-byte loads of
+// the same data took 10% longer).
+// B -> C at n = 32 (two rounds, four barriers): both z transforms and A -> B
+// exchanges come first; round 0's writes of pencil 0 are spread over pencil 1's
+// y transform, and round 1's writes over the four sub-transforms of pencil 0's
+// x transform, whose last combination then runs while round 1's reads are in
+// flight, so that LDS traffic overlaps arithmetic instead of following it.
 // LDS holds HP blocks of n rows with row stride n+1 (padding against bank
 // conflicts; every LDS access is a per-thread base plus an immediate offset).
 // A <-> B only swaps (lane, register) inside the n threads sharing hi: it goes
@@ -410,41 +418,103 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
                     zb[p][ky] = blk[ky * RS + lo];
                 });
                 group_sync<N>();
-                fft<float, N, 1>(zb[p]);
+                if constexpr (P == 1) fft<float, N, 1>(zb[p]);
             });
             cx<float> zc[P][N];
-            sfor<P>([&](auto rI) {   // B -> C, round r delivers C-pencil r (y in [HP r, HP r + HP))
-                constexpr int r = decltype(rI)::value;
-                __syncthreads();
-                sfor<P>([&](auto pI) {
+            if constexpr (P == 2) {
+                // B -> C writes of pencil p, round r, y offset yy in [Y0, Y1)
+                auto put = [&](auto pI, auto rI, auto y0I, auto y1I) {
                     constexpr int p = decltype(pI)::value;
-                    // row kx, column z; the second pencil of hi = 0 (kx = n/2) goes to the
-                    // unread padding column, so row n/2 keeps the zeros of the A -> B exchange
-                    cx<float>* dst = lds + ((P == 2 && p == 1 && hi == 0) ? lo * RS + N : kx_of<N, P>(p, hi) * RS + lo);
-                    sfor<HP>([&](auto yI) {
-                        constexpr int yy = decltype(yI)::value;
+                    constexpr int r = decltype(rI)::value;
+                    constexpr int Y0 = decltype(y0I)::value, Y1 = decltype(y1I)::value;
+                    cx<float>* dst = lds + ((p == 1 && hi == 0) ? lo * RS + N : kx_of<N, P>(p, hi) * RS + lo);
+                    sfor<Y1 - Y0>([&](auto yI) {
+                        constexpr int yy = Y0 + decltype(yI)::value;
                         dst[yy * BS] = zb[p][HP * r + yy];
                     });
+                };
+                auto get = [&](auto rI) {
+                    constexpr int r = decltype(rI)::value;
+                    sfor<N>([&](auto kI) {
+                        constexpr int kx = decltype(kI)::value;
+                        zc[r][kx] = blk[kx * RS + lo];
+                    });
+                };
+                auto acc = [&](auto pI) {
+                    constexpr int p = decltype(pI)::value;
+                    sfor<N>([&](auto xI) {
+                        constexpr int x = decltype(xI)::value;
+                        q[p][x] = fmaf(zc[p][x].x, zc[p][x].y, q[p][x]);
+                    });
+                };
+                using I0 = std::integral_constant<int, 0>;
+                using I1 = std::integral_constant<int, 1>;
+                using IH = std::integral_constant<int, HP>;
+                constexpr int NHOOK = first_radix<N>() + N / first_radix<N>();
+                __builtin_amdgcn_sched_barrier(0);
+                fft<float, N, 1>(zb[0]);
+                __syncthreads();
+                // round 0: pencil 0's writes spread over pencil 1's y transform
+                fft_hook<float, N, 1>(zb[1], [&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    __builtin_amdgcn_sched_barrier(0);
+                    put(I0{}, I0{}, std::integral_constant<int, HP * i / NHOOK>{},
+                        std::integral_constant<int, HP * (i + 1) / NHOOK>{});
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+                put(I1{}, I0{}, I0{}, IH{});
+                __syncthreads();
+                get(I0{});
+                __syncthreads();
+                // round 1: the writes spread over the first-level sub-transforms of pencil 0's
+                // x transform, then the barrier, then the reads overlap its last combination
+                constexpr int NSUB = first_radix<N>();
+                fft_hook<float, N, 1>(zc[0], [&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    if constexpr (i < NSUB) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        constexpr int w0 = 2 * HP * i / NSUB, w1 = 2 * HP * (i + 1) / NSUB;
+                        // w in [w0, w1): pencil w / HP, y offset w % HP (ranges stay in one pencil)
+                        static_assert((w0 / HP) == ((w1 - 1) / HP), "write range crosses pencils");
+                        put(std::integral_constant<int, w0 / HP>{}, I1{}, std::integral_constant<int, w0 % HP>{},
+                            std::integral_constant<int, (w1 - 1) % HP + 1>{});
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if constexpr (i == NSUB - 1) {
+                        __syncthreads();
+                        get(I1{});
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                });
+                acc(I0{});
+                __builtin_amdgcn_sched_barrier(0);
+                load_own(min(j + 1, j_end - 1));
+                __builtin_amdgcn_sched_barrier(0);
+                fft<float, N, 1>(zc[1]);
+                acc(I1{});
+            } else {
+                // one B -> C round: row kx = hi, column z = lo of every y block, then the
+                // C pencil (y = hi, z = lo) from the own block
+                __syncthreads();
+                cx<float>* dst = lds + hi * RS + lo;
+                sfor<HP>([&](auto yI) {
+                    constexpr int yy = decltype(yI)::value;
+                    dst[yy * BS] = zb[0][yy];
                 });
                 __syncthreads();
                 sfor<N>([&](auto kI) {
                     constexpr int kx = decltype(kI)::value;
-                    zc[r][kx] = blk[kx * RS + lo];
+                    zc[0][kx] = blk[kx * RS + lo];
                 });
-            });
-            sfor<P>([&](auto pI) {
-                constexpr int p = decltype(pI)::value;
-                if constexpr (p == P - 1) {   // next term's own-pencil loads overlap this transform
-                    __builtin_amdgcn_sched_barrier(0);
-                    load_own(min(j + 1, j_end - 1));
-                }
+                __builtin_amdgcn_sched_barrier(0);   // next term's own-pencil loads overlap the transform
+                load_own(min(j + 1, j_end - 1));
                 __builtin_amdgcn_sched_barrier(0);
-                fft<float, N, 1>(zc[p]);
+                fft<float, N, 1>(zc[0]);
                 sfor<N>([&](auto xI) {
                     constexpr int x = decltype(xI)::value;
-                    q[p][x] = fmaf(zc[p][x].x, zc[p][x].y, q[p][x]);
+                    q[0][x] = fmaf(zc[0][x].x, zc[0][x].y, q[0][x]);
                 });
-            });
+            }
         }
 
         if constexpr (ONE) {
