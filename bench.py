@@ -29,7 +29,6 @@ sys.path.insert(0, ROOT)
 METRIC = "cells·N³/s of Q(f,f) at N=32³, M=32 (FP32+fix vs FP64, rel err ≤1e-5)"
 UNIT = "cells·N³/s"
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X dense FP32 vector (packed) peak
-PEAK_FP32_UNPACKED_TFLOPS = 78.6    # without packed FP32 (the library is compiled with it off): 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X dense FP64 vector peak
 N_V, T_BOX, NCELL = 32, 8.0, 4096
 N_POLAR, N_AZIM = 8, 4
@@ -481,8 +480,6 @@ def main():
                 peak = PEAK_FP32_VECTOR_TFLOPS if prec == fks.PREC_F32_FIX64 else PEAK_FP64_VECTOR_TFLOPS
                 roof = {"bound": "alu", "achieved": round(fl, 2), "peak": peak, "unit": "TFLOP/s",
                         "frac": round(fl / peak, 4)}
-                if prec == fks.PREC_F32_FIX64:
-                    roof["frac_unpacked_fma"] = round(fl / PEAK_FP32_UNPACKED_TFLOPS, 4)
                 d2_line[name] = {"ms": round(ms2, 4), "value": c2 * n2 * n2 / (ms2 * 1e-3),
                                  "unit": "cells·N²/s", "algorithmic_tflops": round(fl, 2), "roofline": roof}
         d2_line["workload"] = f"{c2} cells, 2D Maxwell molecules, 32^2 on [-9,9]^2, A = 8, f_out"
@@ -526,7 +523,6 @@ def main():
             fl_d = pd.info.flops_per_cell * cd / (msd * 1e-3) / 1e12
             dealias_line["roofline"] = {"bound": "alu", "achieved": round(fl_d, 2), "peak": PEAK_FP32_VECTOR_TFLOPS,
                                         "unit": "TFLOP/s", "frac": round(fl_d / PEAK_FP32_VECTOR_TFLOPS, 4),
-                                        "frac_unpacked_fma": round(fl_d / PEAK_FP32_UNPACKED_TFLOPS, 4),
                                         "flops": "algorithmic: zero-padded transforms, products, truncation"}
             dealias_line["design_traffic"] = {"achieved_gbs": round(gbs, 1), "frac_of_8tbs": round(gbs / 8000.0, 4),
                                               "bytes_per_call": design_bytes,
@@ -689,8 +685,6 @@ def main():
                    "R": plan.info.R, "dt_over_tau": DT_OVER_TAU, "terms_per_cell": plan.info.J},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
-                     "peak_unpacked_fma": PEAK_FP32_UNPACKED_TFLOPS,
-                     "frac_unpacked_fma": round(achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4),
                      "traffic": _traffic_per_launch(), "valu_busy_counters": _valu_busy(), "kernel": kernel_name,
                      "avg_launch_ms": round(terms_ms, 4), "finish_kernel_ms": round(finish_ms, 4),
                      "call_ms": round(avg_call_ms, 4), "flops_per_cell": plan.info.flops_per_cell,
