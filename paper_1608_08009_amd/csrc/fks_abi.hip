@@ -525,7 +525,7 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
         p->table_bytes += tab_elems * sizeof(float);
         p->fused = fused_available(n) && !(d.flags & (FKS_FLAG_FORCE_GENERIC | FKS_FLAG_DEALIAS));
         if (p->fused) p->fused_grid = fused_grid_size(n, p->device);
-        if (p->fused && n <= 32) {   // the kz-pair copy read by the fused kernels at n <= 32
+        if (p->fused) {   // the kz-pair copy read by the fused kernels
             const size_t pair_elems = (size_t)p->J * (n / 2) * n * n * 2;
             if (hipMalloc(&p->d_tab32p, pair_elems * sizeof(float)) != hipSuccess) {
                 plan_free(p);

@@ -1038,7 +1038,7 @@ hipError_t launch48(const fks_segment* const* g, int nseg, void* ws, hipStream_t
         hipError_t e = hipSuccess;
         for (size_t i = 0; i < runs.size() && e == hipSuccess; ++i) {
             const Run& r = runs[i];
-            pc[i] = Piece48{reinterpret_cast<const cx<float>*>(r.s->plan->d_tab32), off, r.s->plan->J};
+            pc[i] = Piece48{reinterpret_cast<const cx<float>*>(r.s->plan->d_tab32p), off, r.s->plan->J};
             e = forward_f32_48(r.s->f + r.c0 * N3, work + off * N3, fh + off * H, (int)r.count, st);
             off += r.count;
         }

@@ -129,7 +129,8 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
     constexpr int N = kN48;
     constexpr int NN = N * N;
     constexpr int N3 = N * N * N;
-    constexpr int H = (N / 2 + 1) * NN;   // table and spectrum stride
+    constexpr int H = (N / 2 + 1) * NN;   // spectrum slot stride
+    constexpr int HT = (N / 2) * NN;      // table stride (planes kz < n/2, kz pairs adjacent)
     constexpr int RSA = N + 1;            // A -> B row stride (floats)
     constexpr int RSC = 17;               // B -> C row stride (complex)
     __shared__ float lds[16 * N * RSA];   // 150528 bytes
@@ -181,40 +182,46 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
         sfor<2>([&](auto rI) { sfor<16>([&](auto mI) { q0[decltype(rI)::value][decltype(mI)::value] = 0.0f; }); });
 
         for (int j = 0; j < pce.J; ++j) {
-            const char* const tjb = reinterpret_cast<const char*>(pce.tab + (size_t)j * H);
-            const uint32_t ob = opaque48(uint32_t(k1 * N + ky) * 8u);
+            const char* const tjb = reinterpret_cast<const char*>(pce.tab + (size_t)j * HT);
+            const uint32_t ob = opaque48(uint32_t(k1 * N + ky) * 16u);
             cx<float> y[N];
             // ---- Z stage: combined products over kz ----
-            // loads run kD planes of kz ahead of their products (rolling buffers), so that a
-            // wave does not wait for L2 once per plane
-            constexpr int kD = 3;
-            cx<float> tv[kD][3], fv[kD][3];
-            auto load_kz = [&](auto kI) {
-                constexpr int kz = decltype(kI)::value;
+            // table and spectrum hold the planes kz = 2m, 2m + 1 side by side, so one 16-byte
+            // load brings both: half the load instructions of 8-byte loads.  The next pair's
+            // loads go out once the current pair's products are formed (kD pairs of buffers;
+            // kD = 2 spills and is slower, and the two other waves of the SIMD cover the wait)
+            constexpr int kD = 1;
+            cx<float> tv[kD][3][2], fv[kD][3][2];
+            auto load_pair = [&](auto mI) {
+                constexpr int m = decltype(mI)::value;
                 sfor<3>([&](auto cI) {
                     constexpr int c2 = decltype(cI)::value;
-                    constexpr uint32_t zo = (kz * NN + 16 * N * c2) * 8u;
-                    tv[kz % kD][c2] = *reinterpret_cast<const cx<float>*>(tjb + (ob + zo));
-                    fv[kz % kD][c2] = *reinterpret_cast<const cx<float>*>(fhb + (ob + zo));
+                    constexpr uint32_t zo = (m * NN + 16 * N * c2) * 16u;
+                    const float4 a = *reinterpret_cast<const float4*>(tjb + (ob + zo));
+                    const float4 b = *reinterpret_cast<const float4*>(fhb + (ob + zo));
+                    tv[m % kD][c2][0] = {a.x, a.y};
+                    tv[m % kD][c2][1] = {a.z, a.w};
+                    fv[m % kD][c2][0] = {b.x, b.y};
+                    fv[m % kD][c2][1] = {b.z, b.w};
                 });
             };
-            sfor<kD>([&](auto kI) { load_kz(kI); });
+            sfor<kD>([&](auto mI) { load_pair(mI); });
             sfor<N / 2>([&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
-                constexpr int b = kz % kD;
-                const cx<float> p0 = cmul(tv[b][0], fv[b][0]), p1 = cmul(tv[b][1], fv[b][1]),
-                                p2 = cmul(tv[b][2], fv[b][2]);
+                constexpr int b = (kz / 2) % kD, e = kz % 2;
+                const cx<float> p0 = cmul(tv[b][0][e], fv[b][0][e]), p1 = cmul(tv[b][1][e], fv[b][1][e]),
+                                p2 = cmul(tv[b][2][e], fv[b][2][e]);
                 const cx<float> s = cadd(p0, cadd(cmul(w3, p1), cmul(w3b, p2)));
                 y[kz] = cmul(tw, s);
                 if constexpr (kz > 0) {
-                    const cx<float> m0 = cmul_conj_b(tv[b][0], fv[b][0]), m1 = cmul_conj_b(tv[b][1], fv[b][1]),
-                                    m2 = cmul_conj_b(tv[b][2], fv[b][2]);
+                    const cx<float> m0 = cmul_conj_b(tv[b][0][e], fv[b][0][e]), m1 = cmul_conj_b(tv[b][1][e], fv[b][1][e]),
+                                    m2 = cmul_conj_b(tv[b][2][e], fv[b][2][e]);
                     const cx<float> sm = cadd(m0, cadd(cmul(conjf(w3), m1), cmul(conjf(w3b), m2)));
                     const cx<float> m = cmul(conjf(tw), sm);
                     const cx<float> mm = {from_mirror_lane(m.x), from_mirror_lane(m.y)};
                     y[N - kz] = self ? m : mm;
                 }
-                if constexpr (kz + kD < N / 2) load_kz(std::integral_constant<int, kz + kD>{});
+                if constexpr (e == 1 && kz / 2 + kD < N / 4) load_pair(std::integral_constant<int, kz / 2 + kD>{});
                 __builtin_amdgcn_sched_barrier(0);
             });
             y[N / 2] = cx<float>{0.0f, 0.0f};

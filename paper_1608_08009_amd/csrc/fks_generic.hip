@@ -98,7 +98,9 @@ __global__ __launch_bounds__(128) void g_pass_y(cx<T>* __restrict__ work, int C)
     });
 }
 
-template <typename T, int N>
+// PAIRS: the planes kz < n/2 in the kz-pair layout of the fused kernels, element (kz, kx, ky)
+// at ((kz/2) n^2 + kx n + ky) 2 + kz % 2; plane n/2 stays at n/2 n^2 + kx n + ky
+template <typename T, int N, bool PAIRS = false>
 __global__ __launch_bounds__(128) void g_fwd_z(const cx<T>* __restrict__ work, cx<T>* __restrict__ fh, int C) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= C * N * N) return;
@@ -117,7 +119,10 @@ __global__ __launch_bounds__(128) void g_fwd_z(const cx<T>* __restrict__ work, c
     sfor<N / 2 + 1>([&](auto I) {
         constexpr int kz = decltype(I)::value;
         cx<T> r = (nyq || kz == N / 2) ? cx<T>{T(0), T(0)} : cx<T>{v[kz].x * s, v[kz].y * s};
-        o[kz * N * N] = r;
+        if constexpr (PAIRS && kz < N / 2)
+            fh[(size_t)c * H + ((kz / 2) * N * N + kx * N + ky) * 2 + kz % 2] = r;
+        else
+            o[kz * N * N] = r;
     });
 }
 
@@ -717,7 +722,7 @@ hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C
     const unsigned grid = (unsigned)((C * 48 * 48 + bs - 1) / bs);
     g_fwd_x<float, 48><<<grid, bs, 0, st>>>(f, work, C);
     g_pass_y<float, 48, -1><<<grid, bs, 0, st>>>(work, C);
-    g_fwd_z<float, 48><<<grid, bs, 0, st>>>(work, fh, C);
+    g_fwd_z<float, 48, true><<<grid, bs, 0, st>>>(work, fh, C);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ struct fks_plan {
     std::vector<double> rad_coef;   // [nq][K]
     double* d_tab64 = nullptr;      // [J][H][2] (omega*alpha, beta) FP64
     float* d_tab32 = nullptr;       // same, rounded to FP32 (FP32 plans only)
-    float* d_tab32p = nullptr;      // fused kernels at n <= 32: d_tab32's planes kz < n/2 as
+    float* d_tab32p = nullptr;      // fused kernels: d_tab32's planes kz < n/2 as
                                     // [J][n/4][n][n][2] complex (kz pairs adjacent)
     fks::GridConst* d_gc = nullptr; // device copy of gc
     int dim = 3;                    // velocity dimension
@@ -94,7 +94,8 @@ hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* w
                            hipStream_t stream);
 
 // n = 48 FP32 forward transform for the on-chip terms kernel (fks_generic.hip): f into the
-// half spectrum [C][n/2+1][n][n] (work: [C][n^3] complex)
+// half spectrum, [C] slots of (n/2+1) n^2 complex with the planes kz < n/2 in the kz-pair
+// layout of d_tab32p (work: [C][n^3] complex)
 hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C, hipStream_t st);
 
 // n = 48 FP32 terms, three workgroups per cell (fks_fused48.hip): resident grid, and the
@@ -102,7 +103,7 @@ hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C
 // counters [8] in device memory, cleared by the call)
 constexpr int kMaxPieces48 = 16;
 struct Piece48 {
-    const cx<float>* tab;   // [J][n/2+1][n][n] balanced FP32 tables
+    const cx<float>* tab;   // [J][n/4][n][n][2] balanced FP32 tables (d_tab32p, kz pairs adjacent)
     int64_t cell0;          // first cell of the piece in the launch's cell order
     int J;
 };
