@@ -603,6 +603,13 @@ def main():
                                         "segment by segment on the multi-pass path",
                        "autotuned_alone": {"fused_one_per_cell": sum(1 for o, c, t in choices if o == 1),
                                            "fused_pairs": sum(1 for o, c, t in choices if o == 0)}}
+        if not args.uneven_quick:
+            # items per resident workgroup that fks_autotune kept for each work queue (the first
+            # segment of each n leads its queue; 0 would be the cost model's 4)
+            leads = {}
+            for sg in segs:
+                leads.setdefault(sg[0].info.n, sg[0].info.queue_items_per_wg)
+            uneven_line["autotuned_queue_items_per_wg"] = {str(k): v for k, v in sorted(leads.items()) if k != 48}
         for pu in plans_u:
             pu.close()
         del segs, segs64

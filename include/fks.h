@@ -119,6 +119,8 @@ typedef struct {
                                   the de-aliased variant counts its zero-padded transforms instead */
     int32_t dim;               /* velocity dimension (2 or 3) */
     int32_t fused_grid;        /* workgroups the fused terms kernel keeps resident (0 if not fused) */
+    int32_t queue_items_per_wg; /* work queues led by this plan: items per resident workgroup
+                                   kept by fks_autotune (0: the cost model's 4) */
 } fks_plan_info;
 
 /*
@@ -211,7 +213,9 @@ fks_status fks_workspace_size(const fks_segment* segs, int32_t nseg, size_t* byt
  *   first), FP32 partial sums, then one FP64 fix over all the group's cells; at
  *   n = 48 one launch of the three-workgroup kernel over all their cells.  Other
  *   segments run alone, in call order.  The grouping depends only on the
- *   segments' plans and sizes, so results are reproducible call to call.
+ *   segments' plans and sizes (and the queue's items per workgroup, which
+ *   fks_autotune may keep in the first segment's plan), so results are
+ *   reproducible call to call.
  * Errors: FKS_ERR_INVALID (NULL plan/f, both outputs NULL, ncell < 0,
  * misaligned arrays, small or misaligned workspace), FKS_ERR_DEVICE (launch
  * failure).
@@ -254,8 +258,14 @@ fks_status fks_collide_batch_static(const fks_segment* segs, int32_t nseg, void*
  * trades launches and accumulator traffic for work-array space.  Later fks_workspace_size and
  * fks_collide_batch calls with the same (plan, ncell) use the kept schedule when
  * the segment runs alone (not in a work queue with other segments of its n, see
- * fks_collide_batch); other sizes keep the built-in cost model.  Schedules change the summation
- * order of the FP32 partial sums only, never the operator.
+ * fks_collide_batch); other sizes keep the built-in cost model.  Segments that
+ * fks_collide_batch would run as one work queue (two or more fused segments of one
+ * n <= 32) are also timed as that queue with 1, 2, 4 or 8 items per resident
+ * workgroup (fewer items carry more terms each: the direction batch of an item); the
+ * fastest is kept in every plan of the group, and a later queue uses the value of
+ * its first segment's plan (fks_plan_info.queue_items_per_wg; 0 = the cost model's
+ * 4).  fks_workspace_size must be asked again after tuning.  Schedules change the
+ * summation order of the FP32 partial sums only, never the operator.
  *   Each segment is evaluated several times (its outputs are overwritten): its
  *   f_out must not overlap f or f_base.  workspace: at least
  *   fks_autotune_workspace_size bytes for the same segments (candidates that do

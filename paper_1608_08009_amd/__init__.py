@@ -66,7 +66,7 @@ class PlanInfo(C.Structure):
         ("n", C.c_int32), ("M", C.c_int32), ("K", C.c_int32), ("J", C.c_int32),
         ("R", C.c_double), ("c_gamma", C.c_double), ("precision", C.c_int32),
         ("fused", C.c_int32), ("table_bytes", C.c_size_t), ("flops_per_cell", C.c_double),
-        ("dim", C.c_int32), ("fused_grid", C.c_int32),
+        ("dim", C.c_int32), ("fused_grid", C.c_int32), ("queue_items_per_wg", C.c_int32),
     ]
 
 
@@ -218,9 +218,21 @@ class Plan:
         _check(lib().fks_plan_create(C.byref(cd), C.c_void_p(_stream_ptr(stream)), C.byref(h)),
                "fks_plan_create")
         self._h = h
+        self._info = self._query()
+
+    def _query(self) -> "PlanInfo":
         info = PlanInfo()
-        _check(lib().fks_plan_query(h, C.byref(info)), "fks_plan_query")
-        self.info = info
+        _check(lib().fks_plan_query(self.handle, C.byref(info)), "fks_plan_query")
+        return info
+
+    @property
+    def info(self) -> "PlanInfo":
+        """fks_plan_query: the fields fixed at creation, and the work-queue knob that
+        fks_autotune may change (queue_items_per_wg), queried again on each access."""
+        if self._h is None:
+            return self._info
+        self._info = self._query()
+        return self._info
 
     @property
     def handle(self):
@@ -230,16 +242,16 @@ class Plan:
 
     @property
     def n(self) -> int:
-        return self.info.n
+        return self._info.n
 
     @property
     def dim(self) -> int:
-        return self.info.dim
+        return self._info.dim
 
     @property
     def cell_size(self) -> int:
         """Velocity nodes per cell: n^dim."""
-        return self.info.n ** self.info.dim
+        return self._info.n ** self._info.dim
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

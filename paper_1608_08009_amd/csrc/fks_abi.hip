@@ -569,6 +569,7 @@ fks_status fks_plan_query(const fks_plan* p, fks_plan_info* info) {
     info->flops_per_cell = p->flops_per_cell;
     info->dim = p->dim;
     info->fused_grid = p->fused ? p->fused_grid : 0;
+    info->queue_items_per_wg = p->queue_ipw;
     return FKS_OK;
 }
 
@@ -841,6 +842,14 @@ static hipError_t collide_one(const fks_segment& g, void* ws, size_t ws_bytes, h
     return g.plan->fused ? collide_fused(g.plan, g, ws, ws_bytes, s) : collide_generic(g.plan, g, ws, ws_bytes, s);
 }
 
+// Work-queue candidates of fks_autotune: items per resident workgroup (the direction batch
+// of an item is about J over the items per cell).  Queues at n = 48 have no such knob.
+static const int kQueueIpw[] = {1, 2, 4, 8};
+static bool tunable_queue(const LaunchGroup& g) { return g.queue && g.segs[0]->plan->desc.n != 48; }
+static void set_queue_ipw(const LaunchGroup& g, int ipw) {
+    for (const fks_segment* s : g.segs) const_cast<fks_plan*>(s->plan)->queue_ipw = ipw;
+}
+
 fks_status fks_autotune_workspace_size(const fks_segment* segs, int32_t nseg, size_t* bytes) {
     if (!bytes || nseg < 0 || (nseg > 0 && !segs)) return FKS_ERR_INVALID;
     size_t mx = 0;
@@ -855,6 +864,16 @@ fks_status fks_autotune_workspace_size(const fks_segment* segs, int32_t nseg, si
         }
         p->tuned = saved;
         mx = std::max(mx, segment_ws(segs[i]));
+    }
+    for (const LaunchGroup& g : batch_groups(segs, nseg)) {
+        if (!tunable_queue(g)) continue;
+        const int saved = g.segs[0]->plan->queue_ipw;
+        for (int ipw : kQueueIpw) {
+            set_queue_ipw(g, ipw);
+            mx = std::max(mx, group_ws(g));
+        }
+        set_queue_ipw(g, saved);
+        mx = std::max(mx, group_ws(g));
     }
     *bytes = mx;
     return FKS_OK;
@@ -927,6 +946,35 @@ fks_status fks_autotune(const fks_segment* segs, int32_t nseg, void* workspace, 
             choice_out[3 * i + 1] = cand[best].chunk;
             choice_out[3 * i + 2] = cand[best].terms;
         }
+    }
+    // work queues (the launch groups fks_collide_batch forms from these segments): items per
+    // resident workgroup, kept in every plan of the group
+    for (const LaunchGroup& grp : batch_groups(segs, nseg)) {
+        if (result != FKS_OK) break;
+        if (!tunable_queue(grp)) continue;
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int ipw : kQueueIpw) {
+            set_queue_ipw(grp, ipw);
+            const size_t need = group_ws(grp);
+            if (need > ws_bytes || !workspace) continue;
+            const int ns = (int)grp.segs.size();
+            float ms = 0.0f;
+            if (collide_fused_queue(grp.segs.data(), ns, workspace, ws_bytes, s) != hipSuccess ||   // warm-up
+                hipEventRecord(ev[0], s) != hipSuccess ||
+                collide_fused_queue(grp.segs.data(), ns, workspace, ws_bytes, s) != hipSuccess ||
+                collide_fused_queue(grp.segs.data(), ns, workspace, ws_bytes, s) != hipSuccess ||
+                hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+                result = FKS_ERR_DEVICE;
+                break;
+            }
+            if (best == 0 || ms < best_ms) {
+                best = ipw;
+                best_ms = ms;
+            }
+        }
+        set_queue_ipw(grp, best);   // 0 (the cost model) if no candidate fitted the workspace
     }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);

@@ -908,9 +908,12 @@ QueuePlan queue_plan(const fks_segment* const* g, int nseg) {
     QueuePlan q;
     q.nseg = nseg;
     const int64_t G = g[0]->plan->fused_grid;
+    // items per resident workgroup: the direction batch of an item is about J / (that many
+    // items per cell); the first segment's plan carries the autotuner's choice
+    const int64_t ipw = g[0]->plan->queue_ipw > 0 ? g[0]->plan->queue_ipw : 4;
     int64_t units = 0;
     for (int i = 0; i < nseg; ++i) units += g[i]->ncell * (g[i]->plan->J + 1);
-    const int64_t len = std::max<int64_t>(4, (units + 4 * G - 1) / (4 * G));
+    const int64_t len = std::max<int64_t>(4, (units + ipw * G - 1) / (ipw * G));
     for (int i = 0; i < nseg; ++i) {
         const int J = g[i]->plan->J;
         q.nchunk[i] = (int)std::min<int64_t>({16, J, std::max<int64_t>(1, (J + len - 1) / len)});

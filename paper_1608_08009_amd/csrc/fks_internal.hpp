@@ -67,6 +67,8 @@ struct fks_plan {
     double flops_per_cell = 0.0;
     int device = 0;
     std::vector<std::pair<int64_t, fks::Schedule>> tuned;   // measured by fks_autotune, per ncell
+    int queue_ipw = 0;              // work queues led by this plan: items per resident workgroup
+                                    // (0: the cost model's 4); kept by fks_autotune
 };
 
 namespace fks {

@@ -79,3 +79,45 @@ def test_rejections_and_tight_workspace_and_2d():
     with fks.Plan(fks.desc2d(16, 6.0, 8, fks.PREC_F64)) as p2:
         g = torch.as_tensor(synth.two_maxwellian_cells_2d(16, 6.0, 4, seed_offset=281), device="cuda")
         assert fks.autotune([(p2, g, torch.empty_like(g), None, 4, 0.0)]) == [(-1, 0, 0)]
+
+
+def test_work_queue_items_per_workgroup_is_tuned_and_followed():
+    # fused segments of one n that fks_collide_batch runs as one work queue are timed as that
+    # queue with 1, 2, 4 or 8 items per resident workgroup; the fastest is kept in every plan of
+    # the group and changes only the term ranges of the items (the summation order of the FP32
+    # partials), so the operator stays within FP32 round-off of the FP64 path
+    n = 16
+    specs = [(1.0, 8, 4, 0, 40), (0.5, 8, 4, 5, 17), (1.0, 4, 4, 0, 33)]
+    plans, segs, refs = [], [], []
+    try:
+        for i, (gamma, npol, naz, K, c) in enumerate(specs):
+            kw = dict(n=n, T=T_BOX, gamma=gamma, n_polar=npol, n_azim=naz, radial_terms=K)
+            p32 = fks.Plan(fks.Desc(**kw, precision=fks.PREC_F32_FIX64))
+            p64 = fks.Plan(fks.Desc(**kw, precision=fks.PREC_F64))
+            plans += [p32, p64]
+            f = synth.two_maxwellian_torch(n, T_BOX, c, "cuda", seed_offset=290 + i)
+            q64 = torch.empty_like(f)
+            fks.collide(p64, f, q_out=q64)
+            segs.append((p32, f, torch.empty_like(f), None, c, 0.0))
+            refs.append(q64)
+        assert all(p.info.queue_items_per_wg == 0 for p in plans[::2])
+        fks.collide_batch(segs)
+        torch.cuda.synchronize()
+        before = [s[2].clone() for s in segs]
+        fks.autotune(segs)
+        kept = {p.info.queue_items_per_wg for p in plans[::2]}
+        assert len(kept) == 1 and kept.pop() in (1, 2, 4, 8)
+        ws = torch.empty(max(fks.workspace_size(segs), 1), dtype=torch.uint8, device="cuda")
+        for s in segs:
+            s[2].fill_(float("nan"))
+        assert _kernels(lambda: fks.collide_batch(segs, workspace=ws)) == 2   # still one queue
+        torch.cuda.synchronize()
+        for s, q64, q0 in zip(segs, refs, before):
+            q = s[2]
+            rel = float(torch.sqrt(torch.sum((q - q64) ** 2) / torch.sum(q64 ** 2)))
+            assert rel <= 1e-5, rel
+            rel0 = float(torch.sqrt(torch.sum((q - q0) ** 2) / torch.sum(q64 ** 2)))
+            assert rel0 <= 1e-5, rel0
+    finally:
+        for p in plans:
+            p.close()
