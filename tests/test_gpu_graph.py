@@ -66,3 +66,27 @@ def test_collide2d_and_bgk_graph_replay():
             fks.collide(p2, f2, q_out=q2)
             fks.bgk(f3, 32, 8.0, 0.8, dim=3, q_out=q3, f_out=g3, dt_over_tau=0.1, nu_rho=True)
         _replays_match(call, [q2, q3, g3])
+
+
+def test_uneven_batch_after_autotune_graph_replay():
+    # one call over segments that form every launch group: a work queue (two n = 16 segments),
+    # the n = 48 three-workgroup kernel over two segments, an n = 24 segment alone, an FP64
+    # multi-pass segment; schedules and the queue's items per workgroup chosen by fks_autotune
+    # first, then the captured call replayed against the eager one
+    specs = [(16, fks.PREC_F32_FIX64, 1.0, 7), (48, fks.PREC_F32_FIX64, 1.0, 3), (16, fks.PREC_F32_FIX64, 0.5, 5),
+             (24, fks.PREC_F32_FIX64, 1.0, 4), (48, fks.PREC_F32_FIX64, 0.0, 2), (16, fks.PREC_F64, 1.0, 6)]
+    plans, segs, outs = [], [], []
+    try:
+        for i, (n, prec, gamma, c) in enumerate(specs):
+            p = fks.Plan(fks.Desc(n=n, T=8.0, gamma=gamma, n_polar=4, n_azim=4, precision=prec))
+            plans.append(p)
+            f = synth.two_maxwellian_torch(n, 8.0, c, "cuda", seed_offset=150 + i)
+            q, g = torch.empty_like(f), torch.empty_like(f)
+            segs.append((p, f, q, g, c, 0.01))
+            outs += [q, g]
+        fks.autotune(segs)
+        ws = torch.empty(max(fks.workspace_size(segs), 1), dtype=torch.uint8, device="cuda")
+        _replays_match(lambda: fks.collide_batch(segs, workspace=ws), outs)
+    finally:
+        for p in plans:
+            p.close()
