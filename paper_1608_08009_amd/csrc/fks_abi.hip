@@ -539,6 +539,11 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
         plan_free(p);
         return FKS_ERR_DEVICE;
     }
+    if (p->d_tab32p) {   // fused plans read only the kz-pair copy; the multi-pass path never runs them
+        (void)hipFree(p->d_tab32);
+        p->d_tab32 = nullptr;
+        p->table_bytes -= tab_elems * sizeof(float);
+    }
     *out = p;
     return FKS_OK;
 }
