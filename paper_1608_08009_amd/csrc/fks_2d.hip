@@ -229,12 +229,24 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
         const cx<R>* tj = tab + (size_t)j * NN + i;
         // (a, b) at (kx = k, ky = i), loaded in groups of kx, each group one scheduling
         // phase ahead of its products (left alone, the compiler waits on every load of
-        // the FP64 kernel before issuing the next)
-        constexpr int NG = (N % 4 == 0) ? 4 : 1, GS = N / NG;
+        // the FP64 kernel before issuing the next).  FP32 tables keep kx = 2m and 2m + 1
+        // side by side (element (kx, ky) at ((kx/2) n + ky) 2 + kx % 2), so one 16-byte load
+        // brings two kx: half the load instructions
+        constexpr bool PAIRS = sizeof(R) == 4;
+        constexpr int NG = PAIRS ? ((N / 2) % 4 == 0 ? 4 : (N / 2) % 3 == 0 ? 3 : 2) : (N % 4 == 0) ? 4 : 1;
+        constexpr int GS = N / NG;
+        static_assert(!PAIRS || GS % 2 == 0, "kx pairs per load group");
         cx<R> ab[N];
         sfor<NG + 1>([&](auto phI) {
             constexpr int ph = decltype(phI)::value;
-            if constexpr (ph < NG)
+            if constexpr (ph < NG && PAIRS)
+                sfor<GS / 2>([&](auto mI) {
+                    constexpr int m = ph * GS / 2 + decltype(mI)::value;
+                    const float4 v = reinterpret_cast<const float4*>(tab + (size_t)j * NN)[m * N + i];
+                    ab[2 * m] = cx<R>{v.x, v.y};
+                    ab[2 * m + 1] = cx<R>{v.z, v.w};
+                });
+            if constexpr (ph < NG && !PAIRS)
                 sfor<GS>([&](auto kI) {
                     constexpr int k = ph * GS + decltype(kI)::value;
                     ab[k] = tj[k * N];

@@ -424,7 +424,17 @@ static fks_status plan_create_2d(fks_plan* p) {
         hipMemcpy(p->d_gc2, &g2, sizeof(GridConst2), hipMemcpyHostToDevice) != hipSuccess)
         return FKS_ERR_DEVICE;
     if (d.precision == FKS_PREC_F32_FIX64) {
-        std::vector<float> ab32(ab.begin(), ab.end());
+        // FP32 copy with kx pairs side by side: (j, kx, ky) at ((j n/2 + kx/2) n + ky) 2 + kx % 2
+        std::vector<float> ab32(ab.size());
+        const size_t nn = (size_t)n * n;
+        for (size_t j = 0; j < (size_t)p->J; ++j)
+            for (int kx = 0; kx < n; ++kx)
+                for (int ky = 0; ky < n; ++ky) {
+                    const size_t src = (j * nn + (size_t)kx * n + ky) * 2;
+                    const size_t dst = ((j * (n / 2) + kx / 2) * n + ky) * 4 + (kx % 2) * 2;
+                    ab32[dst] = (float)ab[src];
+                    ab32[dst + 1] = (float)ab[src + 1];
+                }
         if (hipMalloc(&p->d_tab32, ab32.size() * sizeof(float)) != hipSuccess) return FKS_ERR_NOMEM;
         p->table_bytes += ab32.size() * sizeof(float);
         if (hipMemcpy(p->d_tab32, ab32.data(), ab32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
