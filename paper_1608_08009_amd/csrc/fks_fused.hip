@@ -51,11 +51,14 @@
 // by side, so that each of these loads moves 16 bytes: the number of vector
 // memory instructions, not their bytes, bounds the term loop (8-byte loads of
 // the same data took 10% longer).
-// B -> C at n = 32 (two rounds, four barriers): both z transforms and A -> B
-// exchanges come first; round 0's writes of pencil 0 are spread over pencil 1's
-// y transform, and round 1's writes over the four sub-transforms of pencil 0's
-// x transform, whose last combination then runs while round 1's reads are in
-// flight, so that LDS traffic overlaps arithmetic instead of following it.
+// Exchanges at n = 32 (two pencils per thread; B -> C in two rounds, four
+// barriers): pencil 0's A -> B writes are spread over the sub-transforms of
+// pencil 1's z transform and its reads over that transform's last combination;
+// pencil 1's writes and reads likewise over pencil 0's y transform.  Round 0's
+// B -> C writes of pencil 0 are spread over pencil 1's y transform, and round 1's
+// writes over the four sub-transforms of pencil 0's x transform, whose last
+// combination then runs while round 1's reads are in flight, so that LDS traffic
+// overlaps arithmetic instead of following it.
 // LDS holds HP blocks of n rows with row stride n+1 (padding against bank
 // conflicts; every LDS access is a per-thread base plus an immediate offset).
 // A <-> B only swaps (lane, register) inside the n threads sharing hi: it goes
@@ -399,6 +402,50 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
                 za[1][N / 2] = cx<float>{0.0f, 0.0f};
             }
             cx<float> zb[P][N];
+            if constexpr (P == 2) {
+                // z transforms and A -> B of two pencils: pencil 0's writes go out between the
+                // sub-transforms of pencil 1's z transform and its reads between that
+                // transform's output groups; pencil 1's writes and reads likewise during
+                // pencil 0's y transform (the group lies in one wave, whose LDS accesses are
+                // served in order, so the reads see every write issued before them)
+                constexpr int NSUB = first_radix<N>(), NCMB = N / NSUB;
+                auto a_put = [&](auto pI, auto z0I, auto z1I) {
+                    constexpr int p = decltype(pI)::value;
+                    constexpr int Z0 = decltype(z0I)::value, Z1 = decltype(z1I)::value;
+                    cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // row = this pencil's actual ky
+                    sfor<Z1 - Z0>([&](auto zI) {
+                        constexpr int z = Z0 + decltype(zI)::value;
+                        arow[z] = za[p][z];
+                    });
+                };
+                auto b_get = [&](auto pI, auto k0I, auto k1I) {
+                    constexpr int p = decltype(pI)::value;
+                    constexpr int K0 = decltype(k0I)::value, K1 = decltype(k1I)::value;
+                    sfor<K1 - K0>([&](auto kI) {
+                        constexpr int ky = K0 + decltype(kI)::value;
+                        zb[p][ky] = blk[ky * RS + lo];
+                    });
+                };
+                auto exchange = [&](auto pI, auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    __builtin_amdgcn_sched_barrier(0);
+                    if constexpr (i < NSUB) {
+                        a_put(pI, std::integral_constant<int, N * i / NSUB>{},
+                              std::integral_constant<int, N * (i + 1) / NSUB>{});
+                        if constexpr (i == NSUB - 1) group_sync<N>();
+                    } else {
+                        constexpr int k = i - NSUB;
+                        b_get(pI, std::integral_constant<int, N * k / NCMB>{},
+                              std::integral_constant<int, N * (k + 1) / NCMB>{});
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+                __builtin_amdgcn_sched_barrier(0);
+                fft<float, N, 1>(za[0]);
+                fft_hook<float, N, 1>(za[1], [&](auto iI) { exchange(std::integral_constant<int, 0>{}, iI); });
+                fft_hook<float, N, 1>(zb[0], [&](auto iI) { exchange(std::integral_constant<int, 1>{}, iI); });
+                group_sync<N>();
+            } else
             sfor<P>([&](auto pI) {   // z transform, then A -> B inside the group
                 constexpr int p = decltype(pI)::value;
                 __builtin_amdgcn_sched_barrier(0);
@@ -452,7 +499,6 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
                 using IH = std::integral_constant<int, HP>;
                 constexpr int NHOOK = first_radix<N>() + N / first_radix<N>();
                 __builtin_amdgcn_sched_barrier(0);
-                fft<float, N, 1>(zb[0]);
                 __syncthreads();
                 // round 0: pencil 0's writes spread over pencil 1's y transform
                 fft_hook<float, N, 1>(zb[1], [&](auto iI) {
