@@ -258,7 +258,9 @@ FKS_HD void pin_from(cx<T> (&v)[M]) {
 
 // fft (below) with a hook: hook(I) runs after first-level sub-transform I (I < R) and
 // after output group I - R of the last combination (R <= I < R + N/R), so that a
-// caller can place independent work (LDS traffic, loads) between the transform's parts
+// caller can place independent work (LDS traffic, loads) between the transform's parts.
+// The combination writes x in place (the sub-transforms have consumed the input), so
+// after group k the outputs x[k + (N/R) q], q < R, are final and a hook may use them.
 template <typename T, int N, int SIGN, typename Hook>
 FKS_HD void fft_hook(cx<T> (&x)[N], Hook&& hook) {
     constexpr int R = first_radix<N>();
@@ -270,15 +272,10 @@ FKS_HD void fft_hook(cx<T> (&x)[N], Hook&& hook) {
         pin_from<0>(sub[r]);   // the sub-transform is finished here, not sunk past the hook's work
         hook(rI);
     });
-    cx<T> y[N];
     sfor<M>([&](auto kI) {
         constexpr int k = decltype(kI)::value;
-        combine<T, N, SIGN, R, M, k>(sub, y);
+        combine<T, N, SIGN, R, M, k>(sub, x);
         hook(std::integral_constant<int, R + k>{});
-    });
-    sfor<N>([&](auto kI) {
-        constexpr int k = decltype(kI)::value;
-        x[k] = y[k];
     });
 }
 

@@ -55,7 +55,8 @@
 // barriers): pencil 0's A -> B writes are spread over the sub-transforms of
 // pencil 1's z transform and its reads over that transform's last combination;
 // pencil 1's writes and reads likewise over pencil 0's y transform.  Round 0's
-// B -> C writes of pencil 0 are spread over pencil 1's y transform, and round 1's
+// B -> C writes of pencil 0 are spread over the sub-transforms of pencil 1's y
+// transform, those of pencil 1 go out as its output groups are formed, and round 1's
 // writes over the four sub-transforms of pencil 0's x transform, whose last
 // combination then runs while round 1's reads are in flight, so that LDS traffic
 // overlaps arithmetic instead of following it.
@@ -496,19 +497,26 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
                 };
                 using I0 = std::integral_constant<int, 0>;
                 using I1 = std::integral_constant<int, 1>;
-                using IH = std::integral_constant<int, HP>;
-                constexpr int NHOOK = first_radix<N>() + N / first_radix<N>();
                 __builtin_amdgcn_sched_barrier(0);
                 __syncthreads();
-                // round 0: pencil 0's writes spread over pencil 1's y transform
+                // round 0: pencil 0's writes spread over the sub-transforms of pencil 1's y
+                // transform, and pencil 1's own writes issued as its output groups come out
+                // (group k holds y = k + M q, of which k and k + M belong to round 0)
+                constexpr int NSUBY = first_radix<N>(), MY = N / NSUBY;
+                static_assert(HP == 2 * MY, "round 0 takes two outputs of every group");
                 fft_hook<float, N, 1>(zb[1], [&](auto iI) {
                     constexpr int i = decltype(iI)::value;
                     __builtin_amdgcn_sched_barrier(0);
-                    put(I0{}, I0{}, std::integral_constant<int, HP * i / NHOOK>{},
-                        std::integral_constant<int, HP * (i + 1) / NHOOK>{});
+                    if constexpr (i < NSUBY) {
+                        put(I0{}, I0{}, std::integral_constant<int, HP * i / NSUBY>{},
+                            std::integral_constant<int, HP * (i + 1) / NSUBY>{});
+                    } else {
+                        constexpr int k = i - NSUBY;
+                        put(I1{}, I0{}, std::integral_constant<int, k>{}, std::integral_constant<int, k + 1>{});
+                        put(I1{}, I0{}, std::integral_constant<int, k + MY>{}, std::integral_constant<int, k + MY + 1>{});
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 });
-                put(I1{}, I0{}, I0{}, IH{});
                 __syncthreads();
                 get(I0{});
                 __syncthreads();
