@@ -187,11 +187,12 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
             cx<float> y[N];
             // ---- Z stage: combined products over kz ----
             // table and spectrum hold the planes kz = 2m, 2m + 1 side by side, so one 16-byte
-            // load brings both: half the load instructions of 8-byte loads.  The next pair's
-            // loads go out once the current pair's products are formed (kD pairs of buffers;
-            // kD = 2 spills and is slower, and the two other waves of the SIMD cover the wait)
-            constexpr int kD = 1;
-            cx<float> tv[kD][3][2], fv[kD][3][2];
+            // load brings both: half the load instructions of 8-byte loads.  Pairs 0 and 1 are
+            // loaded before the first products, pair 2 once pair 0's products are formed, and
+            // from then on pair m + 1 once pair m's are (the other waves of the SIMD cover the
+            // rest of the wait; two pairs ahead throughout spills)
+            constexpr int NP = N / 4;   // kz pairs
+            cx<float> tv[NP][3][2], fv[NP][3][2];
             auto load_pair = [&](auto mI) {
                 constexpr int m = decltype(mI)::value;
                 sfor<3>([&](auto cI) {
@@ -199,16 +200,21 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                     constexpr uint32_t zo = (m * NN + 16 * N * c2) * 16u;
                     const float4 a = *reinterpret_cast<const float4*>(tjb + (ob + zo));
                     const float4 b = *reinterpret_cast<const float4*>(fhb + (ob + zo));
-                    tv[m % kD][c2][0] = {a.x, a.y};
-                    tv[m % kD][c2][1] = {a.z, a.w};
-                    fv[m % kD][c2][0] = {b.x, b.y};
-                    fv[m % kD][c2][1] = {b.z, b.w};
+                    tv[m][c2][0] = {a.x, a.y};
+                    tv[m][c2][1] = {a.z, a.w};
+                    fv[m][c2][0] = {b.x, b.y};
+                    fv[m][c2][1] = {b.z, b.w};
                 });
             };
-            sfor<kD>([&](auto mI) { load_pair(mI); });
+            // pairs issued once pair m is done (m = -1: before the first)
+            constexpr auto issued = [](int m) {
+                const int u = m < 1 ? m + 3 : m + 2;
+                return u < NP ? u : NP;
+            };
+            sfor<issued(-1)>([&](auto mI) { load_pair(mI); });
             sfor<N / 2>([&](auto kI) {
                 constexpr int kz = decltype(kI)::value;
-                constexpr int b = (kz / 2) % kD, e = kz % 2;
+                constexpr int b = kz / 2, e = kz % 2;
                 const cx<float> p0 = cmul(tv[b][0][e], fv[b][0][e]), p1 = cmul(tv[b][1][e], fv[b][1][e]),
                                 p2 = cmul(tv[b][2][e], fv[b][2][e]);
                 const cx<float> s = cadd(p0, cadd(cmul(w3, p1), cmul(w3b, p2)));
@@ -221,7 +227,10 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                     const cx<float> mm = {from_mirror_lane(m.x), from_mirror_lane(m.y)};
                     y[N - kz] = self ? m : mm;
                 }
-                if constexpr (e == 1 && kz / 2 + kD < N / 4) load_pair(std::integral_constant<int, kz / 2 + kD>{});
+                if constexpr (e == 1)
+                    sfor<issued(kz / 2) - issued(kz / 2 - 1)>([&](auto qI) {
+                        load_pair(std::integral_constant<int, issued(kz / 2 - 1) + decltype(qI)::value>{});
+                    });
                 __builtin_amdgcn_sched_barrier(0);
             });
             y[N / 2] = cx<float>{0.0f, 0.0f};
