@@ -191,7 +191,8 @@ __global__ __launch_bounds__(kBS) void k_transport(const double* __restrict__ in
         const int sx = source_index(ix, sl[0][kx], nx, bcx, outx);
         const int sy = source_index(iy, sl[1][ky], ny, bcy, outy);
         const int64_t src_col = (int64_t)sy * nx + sx;
-        for (int iz = 0; iz < nz; ++iz) {
+        // one output cell: any source (cell, inflow face or neighbour's message), with branches
+        auto one = [&](int iz) {
             double v[V];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
@@ -224,6 +225,42 @@ __global__ __launch_bounds__(kBS) void k_transport(const double* __restrict__ in
             } else {
                 __builtin_nontemporal_store(v[0], o);
             }
+        };
+        if constexpr (V == 1) {
+            for (int iz = 0; iz < nz; ++iz) one(iz);
+        } else {
+            // Cells whose sources are cells of the grid or inflow faces (all of them, except a
+            // slab's first and last plane, which read messages): the source of each kz is
+            // selected without a branch and read with a 16-byte load of its aligned kz pair
+            // (the two loads coincide when both kz share the source), so that the loads of
+            // several cells are in flight together instead of one load, wait and store per cell.
+            auto src = [&](int iz, int e) -> const double* {
+                bool outz = false;
+                const int sz = SLAB ? iz - sl[2][kz + e] : source_index(iz, sl[2][kz + e], nz, bcz, outz);
+                const int face = outx ? (sx < 0 ? 0 : 1) : outy ? (sy < 0 ? 2 : 3) : outz ? (sz < 0 ? 4 : 5) : -1;
+                return face >= 0 ? bc_f + (int64_t)face * nv + k : in + (sz * ncol + src_col) * nv + k;
+            };
+            constexpr int U = 4;
+            int iz = 0;
+            if (SLAB) one(iz++);
+            const int iz_end = SLAB ? nz - 1 : nz;
+            for (; iz + U <= iz_end; iz += U) {
+                double2 a[U], b[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    a[u] = *reinterpret_cast<const double2*>(src(iz + u, 0));
+                    b[u] = *reinterpret_cast<const double2*>(src(iz + u, 1));
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    __builtin_nontemporal_store(d2v{a[u].x, b[u].y}, reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
+            }
+            for (; iz < iz_end; ++iz) {
+                const double2 a = *reinterpret_cast<const double2*>(src(iz, 0));
+                const double2 b = *reinterpret_cast<const double2*>(src(iz, 1));
+                __builtin_nontemporal_store(d2v{a.x, b.y}, reinterpret_cast<d2v*>(out + (iz * ncol + col) * nv + k));
+            }
+            if (SLAB && nz > 1) one(nz - 1);
         }
     }
 }
