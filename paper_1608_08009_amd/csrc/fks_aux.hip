@@ -244,16 +244,29 @@ __global__ __launch_bounds__(kBS) void k_transport(const double* __restrict__ in
             int iz = 0;
             if (SLAB) one(iz++);
             const int iz_end = SLAB ? nz - 1 : nz;
-            for (; iz + U <= iz_end; iz += U) {
-                double2 a[U], b[U];
+            // when both kz of every lane of the wave share their z shift they share the source
+            // in every cell, and one 16-byte load brings the pair
+            if (__all(sl[2][kz] == sl[2][kz + 1])) {
+                for (; iz + U <= iz_end; iz += U) {
+                    double2 a[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    a[u] = *reinterpret_cast<const double2*>(src(iz + u, 0));
-                    b[u] = *reinterpret_cast<const double2*>(src(iz + u, 1));
+                    for (int u = 0; u < U; ++u) a[u] = *reinterpret_cast<const double2*>(src(iz + u, 0));
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        __builtin_nontemporal_store(d2v{a[u].x, a[u].y}, reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
                 }
+            } else {
+                for (; iz + U <= iz_end; iz += U) {
+                    double2 a[U], b[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    __builtin_nontemporal_store(d2v{a[u].x, b[u].y}, reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
+                    for (int u = 0; u < U; ++u) {
+                        a[u] = *reinterpret_cast<const double2*>(src(iz + u, 0));
+                        b[u] = *reinterpret_cast<const double2*>(src(iz + u, 1));
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        __builtin_nontemporal_store(d2v{a[u].x, b[u].y}, reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
+                }
             }
             for (; iz < iz_end; ++iz) {
                 const double2 a = *reinterpret_cast<const double2*>(src(iz, 0));
