@@ -240,38 +240,39 @@ __global__ __launch_bounds__(kBS) void k_transport(const double* __restrict__ in
                 const int face = outx ? (sx < 0 ? 0 : 1) : outy ? (sy < 0 ? 2 : 3) : outz ? (sz < 0 ? 4 : 5) : -1;
                 return face >= 0 ? bc_f + (int64_t)face * nv + k : in + (sz * ncol + src_col) * nv + k;
             };
-            constexpr int U = 4;
             int iz = 0;
             if (SLAB) one(iz++);
             const int iz_end = SLAB ? nz - 1 : nz;
-            // when both kz of every lane of the wave share their z shift they share the source
-            // in every cell, and one 16-byte load brings the pair
-            if (__all(sl[2][kz] == sl[2][kz + 1])) {
-                for (; iz + U <= iz_end; iz += U) {
-                    double2 a[U];
+            // cells [iz, iz_end) in groups of UU: the loads of a group, then its stores.  SAME:
+            // both kz of every lane share their z shift, hence their source in every cell, and
+            // one 16-byte load brings the pair
+            auto run = [&](auto uI, auto sameI) {
+                constexpr int UU = decltype(uI)::value;
+                constexpr bool SAME = decltype(sameI)::value;
+                for (; iz + UU <= iz_end; iz += UU) {
+                    double2 a[UU], b[UU];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) a[u] = *reinterpret_cast<const double2*>(src(iz + u, 0));
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        __builtin_nontemporal_store(d2v{a[u].x, a[u].y}, reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
-                }
-            } else {
-                for (; iz + U <= iz_end; iz += U) {
-                    double2 a[U], b[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
+                    for (int u = 0; u < UU; ++u) {
                         a[u] = *reinterpret_cast<const double2*>(src(iz + u, 0));
-                        b[u] = *reinterpret_cast<const double2*>(src(iz + u, 1));
+                        if constexpr (!SAME) b[u] = *reinterpret_cast<const double2*>(src(iz + u, 1));
                     }
 #pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        __builtin_nontemporal_store(d2v{a[u].x, b[u].y}, reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
+                    for (int u = 0; u < UU; ++u)
+                        __builtin_nontemporal_store(d2v{a[u].x, SAME ? a[u].y : b[u].y},
+                                                    reinterpret_cast<d2v*>(out + ((iz + u) * ncol + col) * nv + k));
                 }
-            }
-            for (; iz < iz_end; ++iz) {
-                const double2 a = *reinterpret_cast<const double2*>(src(iz, 0));
-                const double2 b = *reinterpret_cast<const double2*>(src(iz, 1));
-                __builtin_nontemporal_store(d2v{a.x, b.y}, reinterpret_cast<d2v*>(out + (iz * ncol + col) * nv + k));
+            };
+            using I1 = std::integral_constant<int, 1>;
+            using I2 = std::integral_constant<int, 2>;
+            using I4 = std::integral_constant<int, 4>;
+            if (__all(sl[2][kz] == sl[2][kz + 1])) {
+                run(I4{}, std::true_type{});
+                run(I2{}, std::true_type{});
+                run(I1{}, std::true_type{});
+            } else {
+                run(I4{}, std::false_type{});
+                run(I2{}, std::false_type{});
+                run(I1{}, std::false_type{});
             }
             if (SLAB && nz > 1) one(nz - 1);
         }
