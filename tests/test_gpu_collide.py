@@ -567,6 +567,43 @@ def test_transport_matches_oracle(bc):
     assert np.array_equal(fa.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
+def test_transport_large_shifts_match_oracle(bc):
+    # CFL 2.6: per-step shifts up to 3 cells (periodic wraps past one period of a 2-cell axis,
+    # inflow faces on Dirichlet axes); even n takes the kz-pair path, 5 planes its groups of
+    # four and one cells, and the kz pairs mix equal and unequal shifts from step to step
+    n, T = 6, 2.0
+    nx, ny, nz = 3, 2, 5
+    dx = 1.0 / nx
+    dt = 2.6 * dx / T
+    rng = synth.rng(81)
+    f0 = rng.uniform(size=(nz, ny, nx, n, n, n))
+    bcf = rng.uniform(size=(6, n, n, n)) + 10.0
+    names = tuple("dirichlet" if b else "periodic" for b in bc)
+    fa, fb = _dev(f0), torch.empty((nz, ny, nx, n, n, n), dtype=torch.float64, device="cuda")
+    # first step at CFL 0.9 with the z displacements started at -v dt / 2, so that no z shift
+    # changes while x and y shift (every kz pair shares its z shift: the one-load path)
+    v = O.velocity_grid(n, T)
+    dt0 = 0.9 * dx / T
+    off = np.zeros((3, n))
+    off[2] = -v * dt0 / 2
+    off_or = off.copy()
+    ref = f0.copy()
+    for step in range(5):
+        h = dt0 if step == 0 else dt
+        fks.transport_shift(fa, fb, nx, ny, nz, dx, bc, n, T, h, off, bc_f=_dev(bcf))
+        off_or, s = O.transport_offsets_step(off_or, n, T, dx, h)
+        if step == 0:
+            assert not s[2].any() and s[0].any()
+        else:
+            assert np.abs(s).max() >= 2
+        ref = O.transport_shift(ref, s, n, bc=names, bc_f=bcf)
+        fa, fb = fb, fa
+    torch.cuda.synchronize()
+    assert np.array_equal(off, off_or)
+    assert np.array_equal(fa.cpu().numpy(), ref)
+
+
 # ---------------------------------------------------------------- spectrum (forward transform of Q or f)
 
 @pytest.mark.parametrize("n,ncell,ws_cells,zn", [(8, 7, 3, False), (12, 5, 5, True), (32, 3, 2, False),
