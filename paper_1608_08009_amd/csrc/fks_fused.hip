@@ -68,7 +68,9 @@
 // n = 24 groups straddle waves and the exchange uses workgroup barriers.  B <-> C
 // crosses waves: P rounds of n^3/P^2 values with workgroup barriers; in every
 // round each group reads back only its own block, so the next group-local
-// exchange can reuse that block without a barrier.
+// exchange can reuse that block without a barrier.  With one pencil per thread
+// (n <= 24) the A -> B and B -> C writes go out as the z and y transforms' output
+// groups are formed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -446,28 +448,31 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
                 fft_hook<float, N, 1>(za[1], [&](auto iI) { exchange(std::integral_constant<int, 0>{}, iI); });
                 fft_hook<float, N, 1>(zb[0], [&](auto iI) { exchange(std::integral_constant<int, 1>{}, iI); });
                 group_sync<N>();
-            } else
-            sfor<P>([&](auto pI) {   // z transform, then A -> B inside the group
-                constexpr int p = decltype(pI)::value;
-                __builtin_amdgcn_sched_barrier(0);
-                fft<float, N, 1>(za[p]);
-                __builtin_amdgcn_sched_barrier(0);
-                cx<float>* arow = blk + ky_of<N, P>(p, hi, lo) * RS;   // row = this pencil's actual ky
-                // a group that straddles waves must not overwrite the block before all of
-                // its threads have read their columns of the previous B -> C round
+            } else {
+                // one pencil: the z transform with the A -> B writes of its output groups (a
+                // group that straddles waves must not overwrite its block before all of its
+                // threads have read their columns of the previous B -> C round), then the reads
                 if constexpr (64 % N != 0) __syncthreads();
-                sfor<N>([&](auto zI) {
-                    constexpr int z = decltype(zI)::value;
-                    arow[z] = za[p][z];
+                constexpr int R1 = first_radix<N>(), M1 = N / R1;
+                cx<float>* arow = blk + ky_of<N, P>(0, hi, lo) * RS;   // row = this pencil's actual ky
+                __builtin_amdgcn_sched_barrier(0);
+                fft_hook<float, N, 1>(za[0], [&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    if constexpr (i >= R1) {   // output group i - R1: z = i - R1 + M1 q
+                        __builtin_amdgcn_sched_barrier(0);
+                        sfor<R1>([&](auto qI) {
+                            constexpr int z = i - R1 + M1 * decltype(qI)::value;
+                            arow[z] = za[0][z];
+                        });
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 });
                 group_sync<N>();
                 sfor<N>([&](auto kI) {
                     constexpr int ky = decltype(kI)::value;
-                    zb[p][ky] = blk[ky * RS + lo];
+                    zb[0][ky] = blk[ky * RS + lo];
                 });
-                group_sync<N>();
-                if constexpr (P == 1) fft<float, N, 1>(zb[p]);
-            });
+            }
             cx<float> zc[P][N];
             if constexpr (P == 2) {
                 // B -> C writes of pencil p, round r, y offset yy in [Y0, Y1)
@@ -547,13 +552,22 @@ __global__ __launch_bounds__(N * N / Cfg<N>::P) void k_terms(TermsArgs<MODE> A) 
                 fft<float, N, 1>(zc[1]);
                 acc(I1{});
             } else {
-                // one B -> C round: row kx = hi, column z = lo of every y block, then the
-                // C pencil (y = hi, z = lo) from the own block
+                // one B -> C round: row kx = hi, column z = lo of every y block, written as the
+                // y transform's output groups come out (every group has read its own block by
+                // the barrier), then the C pencil (y = hi, z = lo) from the own block
                 __syncthreads();
+                constexpr int R1 = first_radix<N>(), M1 = N / R1;
                 cx<float>* dst = lds + hi * RS + lo;
-                sfor<HP>([&](auto yI) {
-                    constexpr int yy = decltype(yI)::value;
-                    dst[yy * BS] = zb[0][yy];
+                fft_hook<float, N, 1>(zb[0], [&](auto iI) {
+                    constexpr int i = decltype(iI)::value;
+                    if constexpr (i >= R1) {   // output group i - R1: y = i - R1 + M1 q
+                        __builtin_amdgcn_sched_barrier(0);
+                        sfor<R1>([&](auto qI) {
+                            constexpr int yy = i - R1 + M1 * decltype(qI)::value;
+                            dst[yy * BS] = zb[0][yy];
+                        });
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 });
                 __syncthreads();
                 sfor<N>([&](auto kI) {
