@@ -258,8 +258,28 @@ __global__ __launch_bounds__((cells_per_block<R, N>() * N)) void k_collide2d(Arg
                 });
             __builtin_amdgcn_sched_barrier(0);
         });
-        fft<R, N, 1>(z);   // over kx: column ky = i, registers over x
-        transpose(z, z);
+        if constexpr (sizeof(R) == 4) {
+            // over kx (column ky = i, registers over x), the transpose writes of each output
+            // group leaving as the group is formed
+            constexpr int R1 = first_radix<N>(), M1 = N / R1;
+            fft_hook<R, N, 1>(z, [&](auto hI) {
+                constexpr int h = decltype(hI)::value;
+                if constexpr (h >= R1) {   // output group h - R1: x = h - R1 + M1 q
+                    __builtin_amdgcn_sched_barrier(0);
+                    sfor<R1>([&](auto qI) {
+                        constexpr int x = h - R1 + M1 * decltype(qI)::value;
+                        blk[x * RS + i] = z[x];
+                    });
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            });
+            cell_sync<N>();
+            sfor<N>([&](auto yI) { z[decltype(yI)::value] = blk[i * RS + decltype(yI)::value]; });
+            cell_sync<N>();
+        } else {
+            fft<R, N, 1>(z);   // over kx: column ky = i, registers over x
+            transpose(z, z);
+        }
         fft<R, N, 1>(z);   // over ky: row x = i, registers over y
         sfor<N>([&](auto yI) {
             constexpr int y = decltype(yI)::value;
