@@ -25,8 +25,11 @@
 //     (0,24), (8,24)) keep their own M.
 //   B stage: pencil (k1, z), registers over ky; the A -> B exchange goes through LDS in
 //     two rounds (real parts, then imaginary parts: 147 KB each).
-//   C stage: pencil (y, z), registers over k1, in three rounds of 16 y (98 KB each);
-//     each round's pencil is transformed and accumulated at once.
+//   C stage: pencil (y, z), registers over k1, in three rounds of 16 y (98 KB each),
+//     round rho the y = 3 yl + rho, which the y transform's 16-point group rho holds;
+//     each round's pencil is transformed and accumulated at once.  The A -> B real
+//     parts of each 16-point group of the z transform, and round 0 of B -> C, go out
+//     as their group is formed.
 // Work items (cell, r) come from one counter per XCD: workgroup b takes items of the
 // cells c with c mod 8 = b mod 8 (blocks are dispatched to XCDs round-robin), so the
 // three residues of a cell share fhat in one XCD's L2.
@@ -78,7 +81,8 @@ __device__ __forceinline__ V opaque48(V v) {
 // 48-point transform (exp(+2 pi i n k / 48)): radix-3 decimation in frequency, then three
 // in-place 16-point transforms, one at a time, so that the live set stays near the 48
 // values; X[k] ends in x[slot48(k)] = x[16 (k mod 3) + k / 3]
-__device__ __forceinline__ void fft48_dif(cx<float> (&x)[48]) {
+template <typename Hook>
+__device__ __forceinline__ void fft48_dif(cx<float> (&x)[48], Hook&& hook) {
     sfor<16>([&](auto nI) {
         constexpr int n1 = decltype(nI)::value;
         cx<float> u[3] = {x[n1], x[n1 + 16], x[n1 + 32]};
@@ -94,8 +98,12 @@ __device__ __forceinline__ void fft48_dif(cx<float> (&x)[48]) {
         sfor<16>([&](auto kI) { s[decltype(kI)::value] = x[16 * q + decltype(kI)::value]; });
         fft<float, 16, 1>(s);
         sfor<16>([&](auto kI) { x[16 * q + decltype(kI)::value] = s[decltype(kI)::value]; });
+        hook(qI);   // slots 16 q .. 16 q + 15 (outputs k = 3 m + q) are final here
     });
     __builtin_amdgcn_sched_barrier(0);
+}
+__device__ __forceinline__ void fft48_dif(cx<float> (&x)[48]) {
+    fft48_dif(x, [](auto) {});
 }
 constexpr int slot48(int k) { return 16 * (k % 3) + k / 3; }
 
@@ -174,8 +182,8 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
         const cx<float> w3 = c_w48.w[16 * r], w3b = c_w48.w[(32 * r) % 48];
         const Piece48 pce = piece_of(A, cell);
         const char* const fhb = reinterpret_cast<const char*>(A.fh + cell * (int64_t)H);
-        // Q+ of this third of the cell: node (3m + r, 16 rho + ub, uz), at byte offset
-        // 4 (3m NN + 16 rho N) + qo from the uniform base; rounds rho = 0, 1 accumulate in
+        // Q+ of this third of the cell: node (3m + r, 3 ub + rho, uz), at byte offset
+        // 4 (3m NN + rho N) + qo from the uniform base; rounds rho = 0, 1 accumulate in
         // registers, round 2 in place in the workspace
         char* const qb = reinterpret_cast<char*>(A.acc + cell * (int64_t)N3 + r * NN);
         float q0[2][16];   // rounds 0 and 1
@@ -234,11 +242,20 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                 __builtin_amdgcn_sched_barrier(0);
             });
             y[N / 2] = cx<float>{0.0f, 0.0f};
-            fft48_dif(y);   // over kz: registers over z (z in slot48(z))
             // ---- A -> B: real parts, then imaginary parts ----
             __syncthreads();   // the previous C round has read the LDS
             float* const arow = lds + opaque48((k1 * N + ky) * RSA);
-            sfor<N>([&](auto zI) { arow[decltype(zI)::value] = y[slot48(decltype(zI)::value)].x; });
+            // over kz (registers over z, z in slot48(z)); each 16-point group's real parts go
+            // out as the group is formed (group q holds z = 3 k + q in slots 16 q + k)
+            fft48_dif(y, [&](auto qI) {
+                constexpr int q = decltype(qI)::value;
+                __builtin_amdgcn_sched_barrier(0);
+                sfor<16>([&](auto kI) {
+                    constexpr int k = decltype(kI)::value;
+                    arow[3 * k + q] = y[16 * q + k].x;
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
             __syncthreads();
             // LDS bases recomputed in each phase (opaque): hoisted out of the term loop, the
             // dozen bases that the paired LDS accesses need would stay live and spill
@@ -256,25 +273,41 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                 constexpr int kk = decltype(kI)::value;
                 bv[kk].y = brow2[kk * RSA];
             });
-            fft48_dif(bv);   // over ky: registers over y (y in slot48(y))
-            // ---- B -> C in three rounds of 16 y; x transform and accumulation per round ----
+            // ---- B -> C in three rounds, round rho the 16 y = 3 yl + rho (slots 16 rho + yl);
+            // x transform and accumulation per round ----
+            __syncthreads();   // every thread has read its imaginary parts
+            // over ky (registers over y, y in slot48(y)); round 0's writes go out as its group
+            // of the transform is formed
+            fft48_dif(bv, [&](auto qI) {
+                if constexpr (decltype(qI)::value == 0) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    cx<float>* const crow = ldc + opaque48(uz * RSC + ub);
+                    sfor<16>([&](auto yI) {
+                        constexpr int yl = decltype(yI)::value;
+                        crow[yl * N * RSC] = bv[yl];
+                    });
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            });
             sfor<3>([&](auto rhoI) {
                 constexpr int rho = decltype(rhoI)::value;
-                __syncthreads();
-                cx<float>* const crow = ldc + opaque48(uz * RSC + ub);
-                sfor<16>([&](auto yI) {
-                    constexpr int yl = decltype(yI)::value;
-                    crow[yl * N * RSC] = bv[slot48(16 * rho + yl)];
-                });
+                if constexpr (rho > 0) {
+                    __syncthreads();
+                    cx<float>* const crow = ldc + opaque48(uz * RSC + ub);
+                    sfor<16>([&](auto yI) {
+                        constexpr int yl = decltype(yI)::value;
+                        crow[yl * N * RSC] = bv[16 * rho + yl];
+                    });
+                }
                 // this round's accumulators, loaded once the round's B values have left the
                 // registers; their latency overlaps the exchange and the x transform
                 float prev[16];
-                const uint32_t qo = opaque48(uint32_t(ub * N + uz) * 4u);
+                const uint32_t qo = opaque48(uint32_t(3 * ub * N + uz) * 4u);
                 sfor<16>([&](auto mI) { prev[decltype(mI)::value] = 0.0f; });
                 if (rho > 1 && j > 0) {
                     sfor<16>([&](auto mI) {
                         constexpr int m = decltype(mI)::value;
-                        constexpr uint32_t mo = (3 * m * NN + 16 * rho * N) * 4u;
+                        constexpr uint32_t mo = (3 * m * NN + rho * N) * 4u;
                         prev[m] = *reinterpret_cast<const float*>(qb + (qo + mo));
                     });
                 }
@@ -288,19 +321,19 @@ __global__ __launch_bounds__(kThreads48) void k_terms48(Args48 A) {
                 fft<float, 16, 1>(xc);   // over k1: x = 3m + r
                 sfor<16>([&](auto mI) {
                     constexpr int m = decltype(mI)::value;
-                    constexpr uint32_t mo = (3 * m * NN + 16 * rho * N) * 4u;
+                    constexpr uint32_t mo = (3 * m * NN + rho * N) * 4u;
                     if constexpr (rho < 2) q0[rho][m] = fmaf(xc[m].x, xc[m].y, q0[rho][m]);
                     else *reinterpret_cast<float*>(qb + (qo + mo)) = fmaf(xc[m].x, xc[m].y, prev[m]);
                 });
             });
         }
         {
-            const uint32_t qo = uint32_t(ub * N + uz) * 4u;
+            const uint32_t qo = uint32_t(3 * ub * N + uz) * 4u;
             sfor<2>([&](auto rI) {
                 constexpr int rho = decltype(rI)::value;
                 sfor<16>([&](auto mI) {
                     constexpr int m = decltype(mI)::value;
-                    *reinterpret_cast<float*>(qb + (qo + uint32_t(3 * m * NN + 16 * rho * N) * 4u)) = q0[rho][m];
+                    *reinterpret_cast<float*>(qb + (qo + uint32_t(3 * m * NN + rho * N) * 4u)) = q0[rho][m];
                 });
             });
         }
