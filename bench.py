@@ -505,29 +505,14 @@ def main():
             torch.cuda.synchronize()
             msd = e0.elapsed_time(e1) / reps
             dealias_line = {"workload": f"{cd} cells of the batch, 32^3, M = 32, zero-padded 48^3 products, "
-                                        "FP32 + FP64 fix, multi-pass path, f_out",
+                                        "FP32 + FP64 fix, products and 48^3 transforms on the on-chip n = 48 "
+                                        "kernel, multi-pass forward and truncating passes, f_out",
                             "ms": round(msd, 3), "value": cd * N_V ** 3 / (msd * 1e-3), "unit": UNIT,
                             "algorithmic_tflops": round(pd.info.flops_per_cell * cd / (msd * 1e-3) / 1e12, 2)}
-            # bytes the multi-pass design moves through HBM (FP32 work arrays, FP64 f):
-            # per term the fused padded z-y pass and the x pass; per cell the forward transform, the
-            # truncating passes, the inverse n-point passes and the fix
-            n, npd, cxb, rb = N_V, 3 * N_V // 2, 8, 4
-            h_half = (n // 2 + 1) * n * n
-            per_term = (h_half * cxb + 2 * n * npd * npd * cxb + 2 * npd ** 3 * rb)   # fused z-y, then x
-            per_cell = (n ** 3 * (8 + 3 * cxb) + h_half * cxb                       # forward
-                        + npd ** 3 * rb + 2 * n * npd * npd * cxb + 2 * n * n * npd * cxb + n ** 3 * cxb
-                        + 3 * n ** 3 * cxb + n ** 3 * rb                               # back to the n grid
-                        + n ** 3 * (rb + 16))                                          # fix and update
-            design_bytes = cd * (pd.info.J * per_term + per_cell)
-            gbs = design_bytes / (msd * 1e-3) / 1e9
             fl_d = pd.info.flops_per_cell * cd / (msd * 1e-3) / 1e12
             dealias_line["roofline"] = {"bound": "alu", "achieved": round(fl_d, 2), "peak": PEAK_FP32_VECTOR_TFLOPS,
                                         "unit": "TFLOP/s", "frac": round(fl_d / PEAK_FP32_VECTOR_TFLOPS, 4),
                                         "flops": "algorithmic: zero-padded transforms, products, truncation"}
-            dealias_line["design_traffic"] = {"achieved_gbs": round(gbs, 1), "frac_of_8tbs": round(gbs / 8000.0, 4),
-                                              "bytes_per_call": design_bytes,
-                                              "bytes": "moved by the multi-pass design (work arrays of the 3n/2 "
-                                                       "grid); not a roofline of the method"}
             del wsd
         print(f"[bench] dealias: {msd:.2f} ms for {cd} cells", file=sys.stderr, flush=True)
 

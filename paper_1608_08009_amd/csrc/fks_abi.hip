@@ -448,6 +448,7 @@ static void plan_free(fks_plan* p) {
     if (p->d_tab64) (void)hipFree(p->d_tab64);
     if (p->d_tab32) (void)hipFree(p->d_tab32);
     if (p->d_tab32p) (void)hipFree(p->d_tab32p);
+    if (p->d_tab48p) (void)hipFree(p->d_tab48p);
     if (p->d_gc) (void)hipFree(p->d_gc);
     if (p->d_gc2) (void)hipFree(p->d_gc2);
     delete p;
@@ -553,6 +554,21 @@ fks_status fks_plan_create(const fks_plan_desc* desc, void* hip_stream, fks_plan
         (void)hipFree(p->d_tab32);
         p->d_tab32 = nullptr;
         p->table_bytes -= tab_elems * sizeof(float);
+    }
+    if (d.precision == FKS_PREC_F32_FIX64 && (d.flags & FKS_FLAG_DEALIAS) && n == 32) {
+        // the products of the 48-point grid run on the n = 48 kernel: the tables zero-padded
+        // to that grid, planes kz < 24 in its kz-pair layout
+        const size_t e48 = (size_t)p->J * 24 * 48 * 48 * 2;
+        if (hipMalloc(&p->d_tab48p, e48 * sizeof(float)) != hipSuccess) {
+            plan_free(p);
+            return FKS_ERR_NOMEM;
+        }
+        p->table_bytes += e48 * sizeof(float);
+        p->grid48 = terms48_grid(p->device);
+        if (embed_tables48(p, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            plan_free(p);
+            return FKS_ERR_DEVICE;
+        }
     }
     *out = p;
     return FKS_OK;

@@ -45,6 +45,8 @@ inline int terms_per_launch(const fks_plan* p, int64_t ncell) {
 inline int chunk_cells(const fks_plan* p, int64_t ncell) {
     const Schedule sc = schedule_for(p, ncell);
     if (sc.chunk > 0) return sc.chunk;
+    // the n = 48 kernel's three workgroups per cell need several cells per resident workgroup
+    if ((p->desc.flags & FKS_FLAG_DEALIAS) && p->d_tab48p) return kChunk;
     if ((p->desc.flags & FKS_FLAG_DEALIAS) || (!generic_multi_terms(p) && p->desc.n >= 32)) return kChunkOneTerm;
     return kChunk;
 }
@@ -614,6 +616,35 @@ hipError_t run(const fks_plan* p, const fks_segment& s, void* ws, hipStream_t st
     return hipSuccess;
 }
 
+// n-grid band index of a wavenumber index k' of the NP grid (FFT order), or -1 outside the band
+// |k| < n/2 (the inverse of pad_pos)
+template <int N, int NP>
+__device__ __forceinline__ int band_of(int kp) {
+    return kp < N / 2 ? kp : kp > NP - N / 2 ? kp - NP + N : -1;
+}
+
+// Band-limited data of the n grid, zero-padded to the NP grid in the layout of the NP = 48
+// kernel: element (kz', kx', ky'), kz' < NP/2, of a slot of S complex at
+// ((kz'/2) NP^2 + kx' NP + ky') 2 + kz' % 2; S = NP/2 NP^2 (tables) or (NP/2 + 1) NP^2
+// (spectra, whose plane kz' = NP/2 stays zero).  Source: slots of H = (n/2+1) n^2 complex,
+// element (kz, kx, ky) at (kz n + kx) n + ky.
+template <int N, int NP>
+__global__ __launch_bounds__(128) void d_embed48(const cx<float>* __restrict__ src, cx<float>* __restrict__ dst,
+                                                 int64_t nslot, int S) {
+    constexpr int H = (N / 2 + 1) * N * N, NN = NP * NP;
+    const int64_t t = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    if (t >= nslot * S) return;
+    const int64_t c = t / S;
+    const int r = (int)(t - c * S);
+    cx<float> v{0.0f, 0.0f};
+    if (r < NP / 2 * NN) {
+        const int m = r / (2 * NN), rem = r % (2 * NN), pos = rem / 2;
+        const int kz = 2 * m + rem % 2, kx = band_of<N, NP>(pos / NP), ky = band_of<N, NP>(pos % NP);
+        if (kz < N / 2 && kx >= 0 && ky >= 0) v = src[c * H + (kz * N + kx) * N + ky];
+    }
+    dst[t] = v;
+}
+
 struct DealiasLayout {
     size_t fh, w1, w2, acc, total;
 };
@@ -650,7 +681,20 @@ hipError_t run_dealias(const fks_plan* p, const fks_segment& s, void* ws, hipStr
         g_fwd_x<T, N><<<grid((int64_t)C * N * N), bs, 0, st>>>(s.f + c0 * (int64_t)NN, w2, C);
         g_pass_y<T, N, -1><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, C);
         g_fwd_z<T, N><<<grid((int64_t)C * N * N), bs, 0, st>>>(w2, fh, C);
-        for (int j = 0; j < p->J; ++j) {
+        bool done = false;
+        if constexpr (sizeof(T) == 4 && N == 32 && NP == 48) {
+            if (p->d_tab48p) {
+                // the NP = 48 kernel over the zero-padded spectrum (in W2) and tables: the same
+                // products, transforms and Re z Im z on the 48-point grid, on chip
+                constexpr int S = 25 * 48 * 48;
+                d_embed48<N, NP><<<grid((int64_t)C * S), bs, 0, st>>>(fh, w2, C, S);
+                const Piece48 pc{reinterpret_cast<const cx<float>*>(p->d_tab48p), 0, p->J};
+                const hipError_t e = terms48(w2, &pc, 1, acc, C, reinterpret_cast<int*>(w1), p->grid48, st);
+                if (e != hipSuccess) return e;
+                done = true;
+            }
+        }
+        for (int j = 0; j < p->J && !done; ++j) {
             d_term_zy<T, N, NP><<<(unsigned)(C * N), 64, 0, st>>>(fh, tab + (size_t)j * H, w2, C);
             d_pad_x<T, N, NP><<<grid((int64_t)C * NP * NP), bs, 0, st>>>(w2, acc, C, j == 0 ? 1 : 0);
         }
@@ -715,6 +759,15 @@ size_t generic_workspace_bytes(const fks_plan* p, int64_t ncell) {
                align256(chunk * NN * sizeof(double));
     return align256(chunk * H * sizeof(cx<float>)) + TB * align256(chunk * NN * sizeof(cx<float>)) +
            align256(chunk * NN * sizeof(float));
+}
+
+hipError_t embed_tables48(const fks_plan* p, hipStream_t st) {
+    if (p->desc.n != 32 || !p->d_tab32 || !p->d_tab48p) return hipErrorInvalidValue;
+    constexpr int S = 24 * 48 * 48;
+    const int64_t total = (int64_t)p->J * S;
+    d_embed48<32, 48><<<(unsigned)((total + 127) / 128), 128, 0, st>>>(
+        reinterpret_cast<const cx<float>*>(p->d_tab32), reinterpret_cast<cx<float>*>(p->d_tab48p), p->J, S);
+    return hipGetLastError();
 }
 
 hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C, hipStream_t st) {

@@ -64,6 +64,9 @@ struct fks_plan {
     size_t table_bytes = 0;
     bool fused = false;             // fks_collide_batch uses the fused kernel
     int fused_grid = 0;             // persistent grid of the fused kernel
+    float* d_tab48p = nullptr;      // FP32 de-aliased plans at n = 32: d_tab32 zero-padded to the
+                                    // 48-point grid in the layout of the n = 48 kernel's tables
+    int grid48 = 0;                 // resident grid of the n = 48 kernel (those plans)
     double flops_per_cell = 0.0;
     int device = 0;
     std::vector<std::pair<int64_t, fks::Schedule>> tuned;   // measured by fks_autotune, per ncell
@@ -99,6 +102,8 @@ hipError_t collide_generic(const fks_plan* plan, const fks_segment& seg, void* w
 // half spectrum, [C] slots of (n/2+1) n^2 complex with the planes kz < n/2 in the kz-pair
 // layout of d_tab32p (work: [C][n^3] complex)
 hipError_t forward_f32_48(const double* f, cx<float>* work, cx<float>* fh, int C, hipStream_t st);
+// FP32 de-aliased plans at n = 32: fill d_tab48p from d_tab32 (fks_generic.hip)
+hipError_t embed_tables48(const fks_plan* p, hipStream_t st);
 
 // n = 48 FP32 terms, three workgroups per cell (fks_fused48.hip): resident grid, and the
 // launch over consecutive cell ranges (pieces) that each share a plan's tables (item

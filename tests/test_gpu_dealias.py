@@ -128,8 +128,9 @@ def test_dealias_equals_aliased_on_band_limited_data_and_differs_on_rough_data()
         assert pd.info.flops_per_cell > pa.info.flops_per_cell
 
 
-def test_dealias_numeric_guard_and_graph_replay():
-    n = 8
+@pytest.mark.parametrize("n", [8, 32])
+def test_dealias_numeric_guard_and_graph_replay(n):
+    # n = 32 in FP32 runs its products on the n = 48 kernel (zero-padded tables and spectrum)
     with fks.Plan(fks.Desc(n=n, T=T_BOX, precision=fks.PREC_F32_FIX64,
                            flags=fks.FLAG_DEALIAS | fks.FLAG_NUMERIC_GUARD)) as plan:
         f = _dev(synth.two_maxwellian_cells(n, T_BOX, 9, seed_offset=440))
